@@ -1,0 +1,171 @@
+/*
+ * tla.h -- C ABI of libtla, batched small dense solvers for MI355X (gfx950).
+ *
+ * The three operations are those of the paper's Fig. 2 (caption): for square
+ * n x n matrices,
+ *   potrf : X^T X = A      A symmetric positive definite, X upper triangular
+ *   trsyl : L X + X U = C  L lower triangular, U upper triangular
+ *   trlyap: L X + X L^T = S   L lower triangular, S and X symmetric
+ * taken literally as printed (plus signs, right-hand side on the right).
+ * The paper generates one routine per size n and picks among algorithm
+ * variants by autotuning (Generator structure paragraph); here every call
+ * handles a batch of independent instances, each with its own n <= n_max.
+ *
+ * Storage: column-major, element (i,j) of instance b at M[b][i + j*ld[b]].
+ * Referenced triangles: potrf reads/writes the upper triangle of A (the
+ * strict lower part is never touched); trsyl reads the lower triangle of L
+ * and the upper triangle of U, reads C and overwrites it with X; trlyap reads
+ * the lower triangles of L and S and overwrites S with the full symmetric X.
+ *
+ * Ownership: every array argument of a compute call (n, ld*, the pointer
+ * arrays, the matrices, info, stat, descriptors) is DEVICE memory owned by the
+ * caller and must stay valid until the call's work on the handle's stream has
+ * finished.  The handle owns its workspace, graph cache, tuning table and MLP
+ * weights.  Compute calls are asynchronous on the handle's stream; info[] and
+ * stat[] are valid after the stream has been synchronised.
+ *
+ * Errors: the return status covers what the host can check (null handle or
+ * pointers with batch > 0, batch < 0, n_max < 0 or above the supported
+ * maximum, an unknown precision, HIP failures).  Per-instance problems go to
+ * info[b]:
+ *    0   success
+ *   -p   argument p of instance b is invalid (-1: n[b] < 0 or n[b] > n_max,
+ *        -2: a leading dimension below max(1, n[b])); the instance is skipped
+ *    k>0 potrf: the leading minor of order k is not positive definite (pivot
+ *        <= 0 or NaN) in the precision that ran last; A is then unspecified.
+ *        trsyl/trlyap: 1 + (i + j*n) of the first zero denominator
+ *        l_ii + u_jj (resp. l_ii + l_jj) in column-major order; X unspecified.
+ * n[b] = 0 is a quick return with info 0.  Nothing crosses the ABI as an
+ * exception.
+ */
+#ifndef TLA_H
+#define TLA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tla_ctx *tla_handle;
+
+typedef enum {
+  TLA_OK = 0,
+  TLA_E_ARG = 1,          /* host-checkable argument error */
+  TLA_E_HIP = 2,          /* a HIP runtime call failed */
+  TLA_E_NOMEM = 3,        /* workspace allocation failed */
+  TLA_E_UNSUPPORTED = 4   /* precision / size / option not built */
+} tla_status;
+
+/* Arithmetic of a call.  Inputs and outputs are FP64 for every value.  The
+ * MIXED_* modes solve in FP32 (tile updates in FP32, FP16 or BF16 on the
+ * matrix cores, FP32 accumulate) and refine in FP64: the residual, the
+ * correction accumulation and the fallback for refinement that does not
+ * converge run in FP64.  The paper itself computes in FP64 only. */
+typedef enum { TLA_F64 = 0, TLA_MIXED_F32 = 1, TLA_MIXED_F16 = 2, TLA_MIXED_BF16 = 3 } tla_prec;
+
+typedef enum { TLA_POTRF = 0, TLA_TRSYL = 1, TLA_TRLYAP = 2 } tla_op;
+
+/* stat.flags bits */
+#define TLA_STAT_CONVERGED 1   /* refinement reached the tolerance */
+#define TLA_STAT_FALLBACK  2   /* refinement stalled or ran out of steps; FP64 solve used */
+#define TLA_STAT_BREAKDOWN 4   /* low-precision solve broke down; FP64 solve used */
+#define TLA_STAT_NONFINITE 8   /* a non-finite input value was seen */
+
+/* Per-instance refinement record (device memory, optional).  eta is the final
+ * FP64 backward error (see tla_set_refine); iters the number of corrections. */
+typedef struct { int iters; int flags; double eta; } tla_stat;
+
+/* Ragged work item: one instance of any operation (device memory array).
+ *   potrf : a = A,             lda
+ *   trsyl : a = L, b = U, c = C/X, lda = ldl, ldb = ldu, ldc
+ *   trlyap: a = L, c = S/X,    lda = ldl, ldc = lds        */
+typedef struct {
+  int op, n;
+  int lda, ldb, ldc, pad_;
+  double *a, *b, *c;
+} tla_desc;
+
+/* ---------------------------------------------------------------- handles */
+/* Create a handle bound to HIP device `device` (made current).  The handle's
+ * stream starts as the device's null stream. */
+tla_status tla_create(tla_handle *h, int device);
+tla_status tla_destroy(tla_handle h);
+/* Subsequent work is enqueued on `stream` (a hipStream_t passed as void*). */
+tla_status tla_set_stream(tla_handle h, void *stream);
+/* Synchronise the handle's stream. */
+tla_status tla_sync(tla_handle h);
+
+/* --------------------------------------------------------- batched solves */
+/* Upper Cholesky X^T X = A (paper Fig. 2a): overwrites the upper triangle of
+ * each A[b] with X.  n, lda, info: int[batch]; A: double*[batch]; stat:
+ * tla_stat[batch] or NULL. */
+tla_status tla_potrf_batched(tla_handle h, tla_prec prec, int batch, int n_max,
+                             const int *n, double *const *A, const int *lda,
+                             int *info, tla_stat *stat);
+
+/* Triangular Sylvester L X + X U = C (paper Fig. 2c): overwrites each C[b]
+ * with X. */
+tla_status tla_trsyl_batched(tla_handle h, tla_prec prec, int batch, int n_max,
+                             const int *n, const double *const *L, const int *ldl,
+                             const double *const *U, const int *ldu,
+                             double *const *C, const int *ldc, int *info, tla_stat *stat);
+
+/* Triangular Lyapunov L X + X L^T = S (paper Fig. 2b): reads the lower
+ * triangle of each S[b] and overwrites the full S[b] with the symmetric X. */
+tla_status tla_trlyap_batched(tla_handle h, tla_prec prec, int batch, int n_max,
+                              const int *n, const double *const *L, const int *ldl,
+                              double *const *S, const int *lds, int *info, tla_stat *stat);
+
+/* Mixed batch of all three operations and uneven n in one persistent launch
+ * (captured as a HIP graph and replayed when the same descriptor array, batch
+ * and precision come again).  d: tla_desc[batch]. */
+tla_status tla_ragged_batched(tla_handle h, tla_prec prec, int batch, int n_max,
+                              const tla_desc *d, int *info, tla_stat *stat);
+
+/* ------------------------------------------------------- plans and tuning */
+/* A plan names the kernel that solves one (op, n bucket, precision):
+ * variant = blocked-algorithm variant (op specific, see tla_variant_name),
+ * tile    = diagonal-block size (8 or 16),
+ * engine  = 0 vector ALU tile updates, 1 matrix-core (MFMA) tile updates,
+ * waves   = wavefronts per instance (1, 2 or 4). */
+typedef struct { int variant, tile, engine, waves; } tla_plan;
+
+/* Which picker chooses plans: the measured tuning table, the MLP cost model
+ * (the table remains the fallback), or the built-in default. */
+typedef enum { TLA_PICK_DEFAULT = 0, TLA_PICK_TABLE = 1, TLA_PICK_MLP = 2 } tla_picker;
+
+/* Force a plan for (op, prec) on every later call (variant < 0 clears it). */
+tla_status tla_set_plan(tla_handle h, tla_op op, tla_prec prec, const tla_plan *plan);
+/* Plan the handle would use for (op, n, prec, batch). */
+tla_status tla_get_plan(tla_handle h, tla_op op, int n, tla_prec prec, int batch, tla_plan *plan);
+/* Number of candidate plans for op and the i-th one (host memory). */
+int tla_num_candidates(tla_op op);
+tla_status tla_candidate(tla_op op, int i, tla_plan *plan);
+const char *tla_variant_name(tla_op op, int variant);
+
+/* Time every candidate plan for each (op, n, prec) of the given lists on
+ * synthetic device inputs (batch instances each, `reps` timed launches per
+ * candidate) and record the fastest in the handle's tuning table; also
+ * stores every measurement.  Synchronous.  ops/ns/precs: host arrays. */
+tla_status tla_tune(tla_handle h, int n_ops, const int *ops, int n_ns, const int *ns,
+                    int n_precs, const int *precs, int batch, int reps);
+/* Measured time (seconds per launch) of one plan, synchronous. */
+tla_status tla_time_plan(tla_handle h, tla_op op, int n, tla_prec prec, int batch,
+                         const tla_plan *plan, int reps, double *seconds);
+/* Tuning table persistence (text, one measurement per line). */
+tla_status tla_save_table(tla_handle h, const char *path);
+tla_status tla_load_table(tla_handle h, const char *path);
+tla_status tla_set_picker(tla_handle h, tla_picker mode);
+
+/* ---------------------------------------------------------- refinement */
+/* Refinement tolerance on the backward error eta (default 1e-13) and the
+ * maximum number of corrections (default 8). */
+tla_status tla_set_refine(tla_handle h, double tau, int max_iter);
+
+const char *tla_status_string(tla_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TLA_H */
