@@ -1,0 +1,293 @@
+"""Python binding of libtla: batched small dense solvers on MI355X.
+
+Thin ctypes layer over the C ABI in include/tla.h (same entry-point names);
+it only marshals arguments.  Every step of the solvers runs in the HIP
+kernels of libtla.so; PyTorch supplies device memory and streams.  There is
+no CPU fallback: if the library is not built, loading it raises.
+
+Matrix convention on the device ("column-major batch"): a float64 CUDA tensor
+M of shape (batch, n, ld) holds instance b's element (i, j) at M[b, j, i],
+i.e. each instance is stored column-major with leading dimension ld.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libtla.so")
+
+# enums of tla.h
+F64, MIXED_F32, MIXED_F16, MIXED_BF16 = 0, 1, 2, 3
+POTRF, TRSYL, TRLYAP = 0, 1, 2
+PICK_DEFAULT, PICK_TABLE, PICK_MLP = 0, 1, 2
+STAT_CONVERGED, STAT_FALLBACK, STAT_BREAKDOWN, STAT_NONFINITE = 1, 2, 4, 8
+OK, E_ARG, E_HIP, E_NOMEM, E_UNSUPPORTED = 0, 1, 2, 3, 4
+PRECS = {"f64": F64, "mixed_f32": MIXED_F32, "mixed_f16": MIXED_F16, "mixed_bf16": MIXED_BF16}
+OPS = {"potrf": POTRF, "trsyl": TRSYL, "trlyap": TRLYAP}
+
+# every exported symbol of include/tla.h
+SYMBOLS = [
+    "tla_create", "tla_destroy", "tla_set_stream", "tla_sync",
+    "tla_potrf_batched", "tla_trsyl_batched", "tla_trlyap_batched", "tla_ragged_batched",
+    "tla_set_plan", "tla_get_plan", "tla_num_candidates", "tla_candidate", "tla_variant_name",
+    "tla_tune", "tla_time_plan", "tla_save_table", "tla_load_table", "tla_set_picker",
+    "tla_set_refine", "tla_status_string",
+]
+
+
+class TlaError(RuntimeError):
+    pass
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int), ("tile", ctypes.c_int), ("engine", ctypes.c_int),
+                ("waves", ctypes.c_int)]
+
+    def __repr__(self):
+        return f"Plan(variant={self.variant}, tile={self.tile}, engine={self.engine}, waves={self.waves})"
+
+    def astuple(self):
+        return (self.variant, self.tile, self.engine, self.waves)
+
+
+class Desc(ctypes.Structure):
+    """tla_desc: one ragged work item."""
+    _fields_ = [("op", ctypes.c_int), ("n", ctypes.c_int), ("lda", ctypes.c_int), ("ldb", ctypes.c_int),
+                ("ldc", ctypes.c_int), ("pad_", ctypes.c_int), ("a", ctypes.c_uint64),
+                ("b", ctypes.c_uint64), ("c", ctypes.c_uint64)]
+
+
+DESC_NP = np.dtype([("op", np.int32), ("n", np.int32), ("lda", np.int32), ("ldb", np.int32),
+                    ("ldc", np.int32), ("pad_", np.int32), ("a", np.uint64), ("b", np.uint64),
+                    ("c", np.uint64)])
+STAT_NP = np.dtype([("iters", np.int32), ("flags", np.int32), ("eta", np.float64)])
+
+_lib = None
+
+
+def lib():
+    """Load libtla.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise TlaError(f"libtla.so not built at {LIB_PATH}; run python -m paper_1906_08613_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, V = ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p
+        D = ctypes.c_double
+        sig = {
+            "tla_create": (I, [ctypes.POINTER(V), I]),
+            "tla_destroy": (I, [V]),
+            "tla_set_stream": (I, [V, V]),
+            "tla_sync": (I, [V]),
+            "tla_potrf_batched": (I, [V, I, I, I, P, P, P, P, P]),
+            "tla_trsyl_batched": (I, [V, I, I, I, P, P, P, P, P, P, P, P, P]),
+            "tla_trlyap_batched": (I, [V, I, I, I, P, P, P, P, P, P, P]),
+            "tla_ragged_batched": (I, [V, I, I, I, P, P, P]),
+            "tla_set_plan": (I, [V, I, I, ctypes.POINTER(Plan)]),
+            "tla_get_plan": (I, [V, I, I, I, I, ctypes.POINTER(Plan)]),
+            "tla_num_candidates": (I, [I]),
+            "tla_candidate": (I, [I, I, ctypes.POINTER(Plan)]),
+            "tla_variant_name": (ctypes.c_char_p, [I, I]),
+            "tla_tune": (I, [V, I, P, I, P, I, P, I, I]),
+            "tla_time_plan": (I, [V, I, I, I, I, ctypes.POINTER(Plan), I, ctypes.POINTER(D)]),
+            "tla_save_table": (I, [V, ctypes.c_char_p]),
+            "tla_load_table": (I, [V, ctypes.c_char_p]),
+            "tla_set_picker": (I, [V, I]),
+            "tla_set_refine": (I, [V, D, I]),
+            "tla_status_string": (ctypes.c_char_p, [I]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str = "tla call"):
+    if status != OK:
+        msg = lib().tla_status_string(status).decode()
+        raise TlaError(f"{what}: {msg} ({status})")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _prec(p):
+    return PRECS[p] if isinstance(p, str) else int(p)
+
+
+# ------------------------------------------------------------------ handle
+class Handle:
+    """Owns a tla_handle bound to a device; work goes on torch's current stream
+    unless `stream` is given."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = device
+        h = ctypes.c_void_p()
+        check(lib().tla_create(ctypes.byref(h), device), "tla_create")
+        self.h = h
+        self.set_stream(stream if stream is not None else torch.cuda.current_stream(device))
+
+    def set_stream(self, stream):
+        self.stream = stream
+        check(lib().tla_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)), "tla_set_stream")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tla_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self):
+        check(lib().tla_sync(self.h), "tla_sync")
+
+    # --------------------------------------------------- raw C-ABI calls
+    def potrf_batched(self, prec, batch, n_max, n, A, lda, info, stat=None):
+        check(lib().tla_potrf_batched(self.h, _prec(prec), batch, n_max, _ptr(n), _ptr(A), _ptr(lda),
+                                      _ptr(info), _ptr(stat)), "tla_potrf_batched")
+
+    def trsyl_batched(self, prec, batch, n_max, n, L, ldl, U, ldu, C, ldc, info, stat=None):
+        check(lib().tla_trsyl_batched(self.h, _prec(prec), batch, n_max, _ptr(n), _ptr(L), _ptr(ldl),
+                                      _ptr(U), _ptr(ldu), _ptr(C), _ptr(ldc), _ptr(info), _ptr(stat)),
+              "tla_trsyl_batched")
+
+    def trlyap_batched(self, prec, batch, n_max, n, L, ldl, S, lds, info, stat=None):
+        check(lib().tla_trlyap_batched(self.h, _prec(prec), batch, n_max, _ptr(n), _ptr(L), _ptr(ldl),
+                                       _ptr(S), _ptr(lds), _ptr(info), _ptr(stat)), "tla_trlyap_batched")
+
+    def ragged_batched(self, prec, batch, n_max, desc, info, stat=None):
+        check(lib().tla_ragged_batched(self.h, _prec(prec), batch, n_max, _ptr(desc), _ptr(info), _ptr(stat)),
+              "tla_ragged_batched")
+
+    # ------------------------------------------------------------- plans
+    def set_plan(self, op, prec, plan=None):
+        if plan is None:
+            p = Plan(-1, 16, 1, 4)
+        else:
+            p = Plan(*plan) if not isinstance(plan, Plan) else plan
+        check(lib().tla_set_plan(self.h, OPS.get(op, op), _prec(prec), ctypes.byref(p)), "tla_set_plan")
+
+    def get_plan(self, op, n, prec, batch):
+        p = Plan()
+        check(lib().tla_get_plan(self.h, OPS.get(op, op), n, _prec(prec), batch, ctypes.byref(p)), "tla_get_plan")
+        return p
+
+    def set_picker(self, mode):
+        check(lib().tla_set_picker(self.h, mode), "tla_set_picker")
+
+    def set_refine(self, tau=1e-13, max_iter=8):
+        check(lib().tla_set_refine(self.h, tau, max_iter), "tla_set_refine")
+
+    def time_plan(self, op, n, prec, batch, plan, reps=5):
+        p = Plan(*plan) if not isinstance(plan, Plan) else plan
+        s = ctypes.c_double()
+        check(lib().tla_time_plan(self.h, OPS.get(op, op), n, _prec(prec), batch, ctypes.byref(p), reps,
+                                  ctypes.byref(s)), "tla_time_plan")
+        return s.value
+
+    def tune(self, ops, ns, precs, batch=1024, reps=3):
+        a = np.array([OPS.get(o, o) for o in ops], dtype=np.int32)
+        b = np.array(ns, dtype=np.int32)
+        c = np.array([_prec(p) for p in precs], dtype=np.int32)
+        check(lib().tla_tune(self.h, len(a), a.ctypes.data_as(ctypes.c_void_p), len(b),
+                             b.ctypes.data_as(ctypes.c_void_p), len(c), c.ctypes.data_as(ctypes.c_void_p),
+                             batch, reps), "tla_tune")
+
+    def save_table(self, path):
+        check(lib().tla_save_table(self.h, path.encode()), "tla_save_table")
+
+    def load_table(self, path):
+        check(lib().tla_load_table(self.h, path.encode()), "tla_load_table")
+
+
+def num_candidates(op):
+    return lib().tla_num_candidates(OPS.get(op, op))
+
+
+def candidate(op, i):
+    p = Plan()
+    check(lib().tla_candidate(OPS.get(op, op), i, ctypes.byref(p)), "tla_candidate")
+    return p
+
+
+def variant_name(op, v):
+    return lib().tla_variant_name(OPS.get(op, op), v).decode()
+
+
+# ---------------------------------------------------------- batch helpers
+def to_device_cm(M, device="cuda", ld=None):
+    """numpy (batch, n, n) indexed [b, i, j] -> column-major batch tensor (batch, n, ld)."""
+    import torch
+    M = np.asarray(M, dtype=np.float64)
+    b, n = M.shape[0], M.shape[-1]
+    ld = ld or n
+    host = np.zeros((b, n, ld), dtype=np.float64)
+    host[:, :, :n] = np.swapaxes(M, 1, 2)
+    return torch.from_numpy(host).to(device)
+
+
+def from_device_cm(t, n=None):
+    """column-major batch tensor (batch, n, ld) -> numpy (batch, n, n) indexed [b, i, j]."""
+    a = t.detach().cpu().numpy()
+    n = n or a.shape[1]
+    return np.ascontiguousarray(np.swapaxes(a[:, :n, :n], 1, 2))
+
+
+class Operands:
+    """Device arrays describing one uniform batch: per-instance n and ld
+    (int32) and pointer arrays (int64 device addresses) for each matrix."""
+
+    def __init__(self, n, *mats, device="cuda"):
+        import torch
+        self.mats = mats
+        self.batch = mats[0].shape[0]
+        self.n_max = n
+        self.n = torch.full((self.batch,), n, dtype=torch.int32, device=device)
+        self.ptrs, self.lds = [], []
+        for m in mats:
+            assert m.dtype == torch.float64 and m.is_contiguous() and m.shape[0] == self.batch
+            stride = m.shape[1] * m.shape[2] * 8
+            base = m.data_ptr()
+            p = torch.arange(self.batch, dtype=torch.int64, device=device) * stride + base
+            self.ptrs.append(p)
+            self.lds.append(torch.full((self.batch,), m.shape[2], dtype=torch.int32, device=device))
+        self.info = torch.zeros(self.batch, dtype=torch.int32, device=device)
+        self.stat = torch.zeros((self.batch, 2), dtype=torch.float64, device=device)  # 16 B per tla_stat
+
+
+def stat_view(stat_tensor):
+    """(batch, 2) float64 tensor holding tla_stat records -> structured numpy array."""
+    return stat_tensor.detach().cpu().numpy().view(STAT_NP).reshape(-1)
+
+
+def potrf(h: Handle, A, prec="f64", ops: Operands | None = None):
+    """In place on the column-major batch A (batch, n, ld)."""
+    ops = ops or Operands(A.shape[1], A)
+    h.potrf_batched(prec, ops.batch, ops.n_max, ops.n, ops.ptrs[0], ops.lds[0], ops.info, ops.stat)
+    return ops
+
+
+def trsyl(h: Handle, L, U, C, prec="f64", ops: Operands | None = None):
+    ops = ops or Operands(C.shape[1], L, U, C)
+    h.trsyl_batched(prec, ops.batch, ops.n_max, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1],
+                    ops.ptrs[2], ops.lds[2], ops.info, ops.stat)
+    return ops
+
+
+def trlyap(h: Handle, L, S, prec="f64", ops: Operands | None = None):
+    ops = ops or Operands(S.shape[1], L, S)
+    h.trlyap_batched(prec, ops.batch, ops.n_max, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1],
+                     ops.info, ops.stat)
+    return ops

@@ -1,0 +1,51 @@
+// Host-side state of a libtla handle.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tla.h"
+#include "tla_registry.h"
+
+namespace tla {
+
+constexpr int kMaxN = 128;  // largest n of the per-instance (LDS-resident) kernels
+
+struct TuneRecord {
+  int op, n, prec, batch;
+  tla_plan plan;
+  double seconds;
+};
+
+struct MlpState;  // learned cost model (tla_mlp.hip)
+
+}  // namespace tla
+
+struct tla_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int lds_limit = 160 * 1024;
+  int num_cu = 256;
+  double tau = 1e-13;
+  int max_iter = 8;
+  int picker = TLA_PICK_TABLE;
+  std::map<int, tla_plan> forced;                 // key op*8 + prec
+  std::vector<tla::TuneRecord> records;           // every measurement
+  std::map<long long, tla_plan> best;             // key (op, n, prec) -> fastest plan
+  tla::MlpState* mlp = nullptr;
+  void release();
+};
+
+namespace tla {
+inline long long table_key(int op, int n, int prec) { return ((long long)op * 16 + prec) * 100000 + n; }
+bool table_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* p);
+bool mlp_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* p);
+void mlp_release(tla_ctx* h);
+tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& a);
+bool plan_valid(int op, const tla_plan& p);
+int num_candidates(int op);
+bool candidate(int op, int i, tla_plan* p);
+tla_plan default_plan(int op, int n, int prec);
+}  // namespace tla

@@ -1,0 +1,29 @@
+// Internal types shared by the host library and its kernels.
+#pragma once
+#include "../../include/tla.h"
+
+namespace tla {
+
+// Arguments of every batched kernel (device pointers, passed by value).
+//   potrf : c = A (in/out), ldc
+//   trsyl : a = L, b = U, c = C -> X
+//   trlyap: a = L, c = S -> X
+struct KArgs {
+  int batch, n_max;
+  int ntmax;             // tiles per dimension the LDS was sized for
+  int max_iter;          // refinement: maximum number of corrections
+  double tau;            // refinement: target backward error
+  const int* n;
+  const double* const* a;
+  const int* lda;
+  const double* const* b;
+  const int* ldb;
+  double* const* c;
+  const int* ldc;
+  int* info;
+  tla_stat* stat;
+  double* work;          // per-instance FP64 workspace (mixed path), may be null
+  long long work_stride; // doubles per instance in `work`
+};
+
+}  // namespace tla

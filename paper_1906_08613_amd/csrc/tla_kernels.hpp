@@ -1,0 +1,215 @@
+// Batched kernels: one workgroup per instance, operands staged in LDS.
+//
+// Every kernel reads the instance's n and leading dimensions from device
+// arrays, validates them (info = -1 / -2 and skip), loads the referenced
+// triangles with column-coalesced loads into LDS, runs one blocked variant
+// and writes the referenced part of the result back in place.
+#pragma once
+#include <climits>
+
+#include "tla_solvers.hpp"
+#include "tla_internal.h"
+
+namespace tla {
+
+// ----------------------------------------------------------- global views
+// Read-only view of a caller matrix in global memory, with the coordinates
+// of the underlying column-major matrix.  Entries outside n x n or outside
+// the referenced triangle (tri < 0: lower, tri > 0: upper) read as zero, so
+// padded tiles need no special casing.
+template <class T>
+struct GView {
+  const double* p;
+  int ld, n, tri;
+  int r0, c0;
+  bool tr;
+  TLA_DI T operator()(int i, int j) const {
+    const int r = tr ? r0 + j : r0 + i;
+    const int c = tr ? c0 + i : c0 + j;
+    const bool ok = r < n && c < n && (tri == 0 || (tri < 0 ? r >= c : r <= c));
+    return ok ? T(p[r + (size_t)c * ld]) : T(0);
+  }
+  TLA_DI GView sub(int i0, int j0) const {
+    GView v = *this;
+    if (tr) { v.r0 += j0; v.c0 += i0; } else { v.r0 += i0; v.c0 += j0; }
+    return v;
+  }
+  TLA_DI GView t() const { GView v = *this; v.tr = !tr; return v; }
+};
+template <class T>
+TLA_DI GView<T> gview(const double* p, int ld, int n, int tri) { return GView<T>{p, ld, n, tri, 0, 0, false}; }
+
+// ------------------------------------------------------ ingest / egress
+// Copies the n x n global matrix into the np x np LDS matrix (ld = ldw),
+// keeping the part selected by `part` and writing `pad` on the padded
+// diagonal and zero elsewhere.  part: 0 full, -1 lower (i >= j), +1 upper,
+// 2 lower mirrored into both halves (symmetric input given by its lower
+// triangle).  Columns are spread over waves, rows over lanes (coalesced).
+template <class T, int NW>
+TLA_DI void ingest(T* W, int ldw, int np, const double* G, int ldg, int n, int part, T pad) {
+  const int w = wave_id(), l = lane_id();
+  for (int j = w; j < np; j += NW) {
+    for (int i = l; i < np; i += 64) {
+      T v;
+      if (i < n && j < n) {
+        if (part == 0) v = T(G[i + (size_t)j * ldg]);
+        else if (part == -1) v = i >= j ? T(G[i + (size_t)j * ldg]) : T(0);
+        else if (part == 1) v = i <= j ? T(G[i + (size_t)j * ldg]) : T(0);
+        else v = i >= j ? T(G[i + (size_t)j * ldg]) : T(G[j + (size_t)i * ldg]);
+      } else {
+        v = (i == j) ? pad : T(0);
+      }
+      W[i + j * ldw] = v;
+    }
+  }
+}
+
+// Writes the n x n result back: part 0 full, +1 upper triangle only,
+// 2 symmetric from the lower triangle.
+template <class T, int NW>
+TLA_DI void egress(double* G, int ldg, int n, const T* W, int ldw, int part) {
+  const int w = wave_id(), l = lane_id();
+  for (int j = w; j < n; j += NW) {
+    for (int i = l; i < n; i += 64) {
+      if (part == 1 && i > j) continue;
+      const T v = (part == 2 && i < j) ? W[j + i * ldw] : W[i + j * ldw];
+      G[i + (size_t)j * ldg] = double(v);
+    }
+  }
+}
+
+// first zero denominator d_ij = a_i + b_j (column-major index + 1) into *info
+template <class VA, class VB>
+TLA_DI void scan_zero_denoms(const VA& A, const VB& B, int n, bool lower_only, int* info) {
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int j = e / n, i = e - j * n;
+    if (lower_only && i < j) continue;
+    if (A(i, i) + B(j, j) == 0.0) atomicMin(info, 1 + e);
+  }
+}
+
+TLA_DI bool validate(const KArgs& g, int b, int& n) {
+  n = g.n[b];
+  int bad = 0;
+  if (n < 0 || n > g.n_max) bad = -1;
+  else {
+    const int m = n > 1 ? n : 1;
+    if (g.ldc[b] < m) bad = -2;
+    if (g.lda && g.lda[b] < m) bad = -2;
+    if (g.ldb && g.ldb[b] < m) bad = -2;
+  }
+  if (bad != 0 || n == 0) {
+    if (threadIdx.x == 0) {
+      g.info[b] = bad;
+      if (g.stat) { g.stat[b].iters = 0; g.stat[b].flags = 0; g.stat[b].eta = 0.0; }
+    }
+    return false;
+  }
+  return true;
+}
+
+// LDS bytes of the FP64 kernels for tile count ntmax per dimension.
+__host__ __device__ inline size_t lds_mat_bytes(int ntmax, int tb, int elem) {
+  const size_t np = (size_t)ntmax * tb;
+  return np * (np + 1) * elem;
+}
+__host__ __device__ inline size_t lds_scratch_bytes(int nw, int tb, int elem) {
+  return (size_t)nw * 4 * tb * elem + 16;
+}
+
+// ================================================================ FP64
+template <int TB, int ENG, int NW, int VAR>
+__global__ __launch_bounds__(NW * 64) void k_potrf_f64(KArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x;
+  int n;
+  if (!validate(g, b, n)) return;
+  const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
+  double* A = reinterpret_cast<double*>(smem);
+  double* wb = A + (size_t)g.ntmax * TB * (g.ntmax * TB + 1);
+  int* s_info = reinterpret_cast<int*>(wb + NW * 4 * TB);
+  if (threadIdx.x == 0) *s_info = 0;
+  ingest<double, NW>(A, ld, np, g.c[b], g.ldc[b], n, +1, 1.0);
+  __syncthreads();
+  Ctx<double> cx{n, nt, wb + wave_id() * 4 * TB, s_info};
+  potrf_blocked<double, TB, ENG, NW, VAR>(colmajor(A, ld), cx);
+  __syncthreads();
+  egress<double, NW>(g.c[b], g.ldc[b], n, A, ld, 1);
+  if (threadIdx.x == 0) {
+    g.info[b] = *s_info;
+    if (g.stat) { g.stat[b].iters = 0; g.stat[b].flags = 0; g.stat[b].eta = 0.0; }
+  }
+}
+
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS>
+__global__ __launch_bounds__(NW * 64) void k_trsyl_f64(KArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x;
+  int n;
+  if (!validate(g, b, n)) return;
+  const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
+  const size_t mat = (size_t)g.ntmax * TB * (g.ntmax * TB + 1);
+  double* X = reinterpret_cast<double*>(smem);
+  double* Ls = X + mat;
+  double* Us = Ls + mat;
+  double* wb = LU_LDS ? Us + mat : Ls;
+  int* s_info = reinterpret_cast<int*>(wb + NW * 4 * TB);
+  if (threadIdx.x == 0) *s_info = INT_MAX;
+  ingest<double, NW>(X, ld, np, g.c[b], g.ldc[b], n, 0, 0.0);
+  if constexpr (LU_LDS) {
+    ingest<double, NW>(Ls, ld, np, g.a[b], g.lda[b], n, -1, 0.0);
+    ingest<double, NW>(Us, ld, np, g.b[b], g.ldb[b], n, +1, 0.0);
+  }
+  __syncthreads();
+  Ctx<double> cx{n, nt, wb + wave_id() * 4 * TB, s_info};
+  if constexpr (LU_LDS) {
+    scan_zero_denoms(colmajor(Ls, ld), colmajor(Us, ld), n, false, s_info);
+    trsyl_blocked<double, TB, ENG, NW, VAR>(colmajor(X, ld), colmajor(Ls, ld), colmajor(Us, ld), cx);
+  } else {
+    const GView<double> L = gview<double>(g.a[b], g.lda[b], n, -1);
+    const GView<double> U = gview<double>(g.b[b], g.ldb[b], n, +1);
+    scan_zero_denoms(L, U, n, false, s_info);
+    trsyl_blocked<double, TB, ENG, NW, VAR>(colmajor(X, ld), L, U, cx);
+  }
+  __syncthreads();
+  egress<double, NW>(g.c[b], g.ldc[b], n, X, ld, 0);
+  if (threadIdx.x == 0) {
+    g.info[b] = *s_info == INT_MAX ? 0 : *s_info;
+    if (g.stat) { g.stat[b].iters = 0; g.stat[b].flags = 0; g.stat[b].eta = 0.0; }
+  }
+}
+
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS>
+__global__ __launch_bounds__(NW * 64) void k_trlyap_f64(KArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x;
+  int n;
+  if (!validate(g, b, n)) return;
+  const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
+  const size_t mat = (size_t)g.ntmax * TB * (g.ntmax * TB + 1);
+  double* X = reinterpret_cast<double*>(smem);
+  double* Ls = X + mat;
+  double* wb = LU_LDS ? Ls + mat : Ls;
+  int* s_info = reinterpret_cast<int*>(wb + NW * 4 * TB);
+  if (threadIdx.x == 0) *s_info = INT_MAX;
+  ingest<double, NW>(X, ld, np, g.c[b], g.ldc[b], n, 2, 0.0);
+  if constexpr (LU_LDS) ingest<double, NW>(Ls, ld, np, g.a[b], g.lda[b], n, -1, 0.0);
+  __syncthreads();
+  Ctx<double> cx{n, nt, wb + wave_id() * 4 * TB, s_info};
+  if constexpr (LU_LDS) {
+    scan_zero_denoms(colmajor(Ls, ld), colmajor(Ls, ld), n, true, s_info);
+    trlyap_blocked<double, TB, ENG, NW, VAR>(colmajor(X, ld), colmajor(Ls, ld), cx);
+  } else {
+    const GView<double> L = gview<double>(g.a[b], g.lda[b], n, -1);
+    scan_zero_denoms(L, L, n, true, s_info);
+    trlyap_blocked<double, TB, ENG, NW, VAR>(colmajor(X, ld), L, cx);
+  }
+  __syncthreads();
+  egress<double, NW>(g.c[b], g.ldc[b], n, X, ld, 2);
+  if (threadIdx.x == 0) {
+    g.info[b] = *s_info == INT_MAX ? 0 : *s_info;
+    if (g.stat) { g.stat[b].iters = 0; g.stat[b].flags = 0; g.stat[b].eta = 0.0; }
+  }
+}
+
+}  // namespace tla

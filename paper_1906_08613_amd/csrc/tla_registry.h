@@ -1,0 +1,17 @@
+// Kernel lookup by plan.  Each operation/precision family exports one lookup
+// function; `te` encodes (tile, engine): 0 = (8, vector ALU), 1 = (16, vector
+// ALU), 2 = (16, matrix cores); `nwi` encodes waves per instance 1 / 2 / 4.
+#pragma once
+#include "tla_internal.h"
+
+namespace tla {
+typedef void (*KFn)(KArgs);
+constexpr int kNumTE = 3, kNumNW = 3;
+inline int te_index(int tile, int engine) { return tile == 8 ? 0 : (engine ? 2 : 1); }
+inline int nw_index(int waves) { return waves == 1 ? 0 : (waves == 2 ? 1 : 2); }
+inline int te_tile(int te) { return te == 0 ? 8 : 16; }
+
+KFn potrf_f64_kernel(int var, int te, int nwi);
+KFn trsyl_f64_kernel(int var, int te, int nwi, bool lu_lds);
+KFn trlyap_f64_kernel(int var, int te, int nwi, bool lu_lds);
+}  // namespace tla

@@ -1,0 +1,320 @@
+// Tile-level building blocks for the batched small solvers on CDNA4 (gfx950).
+//
+// One workgroup of NW wavefronts works on one problem instance whose operands
+// sit in LDS (or, for the largest sizes, are read through the caches).  The
+// matrix is cut into TB x TB tiles (TB = 16 for the matrix-core engine, 8 or
+// 16 for the vector-ALU engine).  A tile that a wave is working on lives in
+// registers, spread over the 64 lanes in the accumulator layout of the 16x16
+// MFMA instructions, so a tile update can feed the matrix cores directly and
+// the diagonal-tile solvers can work on the same registers.
+//
+// Accumulator layouts (measured on gfx950 with an in-bounds probe):
+//   v_mfma_f64_16x16x4f64 : lane l holds rows (l>>4) + 4r, r = 0..3, column l&15
+//   v_mfma_f32_16x16x4f32 / _16x16x16{f16,bf16}: rows 4(l>>4) + r, column l&15
+// A operand (16 x K slice): lane l holds A[l&15][k-block(l>>4)];
+// B operand (K x 16 slice): lane l holds B[k-block(l>>4)][l&15].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tla {
+
+#define TLA_DI __device__ __forceinline__
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+
+enum Engine { ENG_VALU = 0, ENG_MFMA = 1, ENG_MFMA_F16 = 2, ENG_MFMA_BF16 = 3 };
+
+TLA_DI int lane_id() { return threadIdx.x & 63; }
+TLA_DI int wave_id() { return threadIdx.x >> 6; }
+
+// Orders LDS traffic between lanes of one wavefront: the LDS serves one
+// wave's requests in issue order, so waiting for the outstanding ones and
+// stopping the compiler from moving memory accesses across is enough.
+TLA_DI void wave_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// --------------------------------------------------------------- views
+// Strided matrix view: element (i, j) at p[i*rs + j*cs].  Column-major
+// storage with leading dimension ld is (rs, cs) = (1, ld); t() transposes.
+template <class T>
+struct View {
+  T* p;
+  int rs, cs;
+  TLA_DI T operator()(int i, int j) const { return p[i * rs + j * cs]; }
+  TLA_DI T& at(int i, int j) const { return p[i * rs + j * cs]; }
+  TLA_DI View sub(int i0, int j0) const { return View{p + i0 * rs + j0 * cs, rs, cs}; }
+  TLA_DI View t() const { return View{p, cs, rs}; }
+};
+template <class T>
+TLA_DI View<T> colmajor(T* p, int ld) { return View<T>{p, 1, ld}; }
+
+// ----------------------------------------------------------- fragments
+template <class T> struct Frag;
+template <> struct Frag<double> {
+  typedef d4 acc;
+  static TLA_DI int row(int g, int r) { return g + 4 * r; }
+  static TLA_DI acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Frag<float> {
+  typedef f4 acc;
+  static TLA_DI int row(int g, int r) { return 4 * g + r; }
+  static TLA_DI acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// A TB x TB tile in registers: EPL elements per lane.
+//   TB = 16: lane l holds column l&15, rows Frag<T>::row(l>>4, r), r < 4
+//   TB =  8: lane l holds column l&7,  row l>>3
+template <class T, int TB>
+struct Tile {
+  static constexpr int EPL = TB * TB / 64;
+  T v[EPL];
+};
+
+template <class T, int TB>
+TLA_DI int trow(int lane, int r) {
+  if constexpr (TB == 16) return Frag<T>::row(lane >> 4, r);
+  else return lane >> 3;
+}
+template <int TB>
+TLA_DI int tcol(int lane) { return lane & (TB - 1); }
+
+template <class T, int TB, class V>
+TLA_DI void tload(Tile<T, TB>& c, const V& M) {
+  const int l = lane_id(), j = tcol<TB>(l);
+#pragma unroll
+  for (int r = 0; r < Tile<T, TB>::EPL; ++r) c.v[r] = M(trow<T, TB>(l, r), j);
+}
+template <class T, int TB>
+TLA_DI void tstore(const Tile<T, TB>& c, const View<T>& M) {
+  const int l = lane_id(), j = tcol<TB>(l);
+#pragma unroll
+  for (int r = 0; r < Tile<T, TB>::EPL; ++r) M.at(trow<T, TB>(l, r), j) = c.v[r];
+}
+template <class T, int TB>
+TLA_DI void tzero(Tile<T, TB>& c) {
+#pragma unroll
+  for (int r = 0; r < Tile<T, TB>::EPL; ++r) c.v[r] = T(0);
+}
+
+// ------------------------------------------------------ tile products
+// c -= A * B for TB x TB operand views A, B (already offset to the tile).
+template <class T, int TB, int ENG>
+struct Gemm;
+
+// Matrix cores in the working precision (f64 16x16x4 or f32 16x16x4).
+template <class T>
+struct Gemm<T, 16, ENG_MFMA> {
+  template <class VA, class VB>
+  static TLA_DI void sub(Tile<T, 16>& c, const VA& A, const VB& B) {
+    const int l = lane_id(), i = l & 15, kq = l >> 4;
+    typename Frag<T>::acc acc = {c.v[0], c.v[1], c.v[2], c.v[3]};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = Frag<T>::mma(-A(i, 4 * kk + kq), B(4 * kk + kq, i), acc);
+    c.v[0] = acc[0]; c.v[1] = acc[1]; c.v[2] = acc[2]; c.v[3] = acc[3];
+  }
+};
+
+// Matrix cores in FP16 / BF16 with FP32 accumulation (FP32 working precision
+// only): the operands are rounded to the 16-bit type, K = 16 in one step.
+template <>
+struct Gemm<float, 16, ENG_MFMA_F16> {
+  template <class VA, class VB>
+  static TLA_DI void sub(Tile<float, 16>& c, const VA& A, const VB& B) {
+    const int l = lane_id(), i = l & 15, kq = l >> 4;
+    h4 a, b;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      a[e] = (_Float16)(-A(i, 4 * kq + e));
+      b[e] = (_Float16)(B(4 * kq + e, i));
+    }
+    f4 acc = {c.v[0], c.v[1], c.v[2], c.v[3]};
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+    c.v[0] = acc[0]; c.v[1] = acc[1]; c.v[2] = acc[2]; c.v[3] = acc[3];
+  }
+};
+template <>
+struct Gemm<float, 16, ENG_MFMA_BF16> {
+  template <class VA, class VB>
+  static TLA_DI void sub(Tile<float, 16>& c, const VA& A, const VB& B) {
+    const int l = lane_id(), i = l & 15, kq = l >> 4;
+    s4 a, b;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      a[e] = __builtin_bit_cast(short, (__bf16)(-A(i, 4 * kq + e)));
+      b[e] = __builtin_bit_cast(short, (__bf16)(B(4 * kq + e, i)));
+    }
+    f4 acc = {c.v[0], c.v[1], c.v[2], c.v[3]};
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    c.v[0] = acc[0]; c.v[1] = acc[1]; c.v[2] = acc[2]; c.v[3] = acc[3];
+  }
+};
+
+// Vector ALU: each lane accumulates its own elements, k outermost.
+template <class T, int TB>
+struct Gemm<T, TB, ENG_VALU> {
+  template <class VA, class VB>
+  static TLA_DI void sub(Tile<T, TB>& c, const VA& A, const VB& B) {
+    const int l = lane_id(), j = tcol<TB>(l);
+#pragma unroll 4
+    for (int k = 0; k < TB; ++k) {
+      const T b = B(k, j);
+#pragma unroll
+      for (int r = 0; r < Tile<T, TB>::EPL; ++r) c.v[r] -= A(trow<T, TB>(l, r), k) * b;
+    }
+  }
+};
+
+// ------------------------------------------------------ tile solvers
+// All solvers run on one wavefront; `buf` is that wave's private LDS scratch
+// of at least 3*TB elements.
+
+// Triangular Sylvester on one tile:  Lt X + X Ut = c  (Lt lower, Ut upper,
+// TB x TB views), overwriting c with X.  Element (i, j) is final once every
+// (k, j), k < i and (i, k), k < j is; all elements on the anti-diagonal
+// i + j = s are finalised together and then subtract their contribution
+// from the elements below them in their column and right of them in their
+// row.  Elements with i >= ni or j >= nj (padding) are forced to zero.
+template <class T, int TB, class VL, class VU>
+TLA_DI void tile_sylv(Tile<T, TB>& c, const VL& Lt, const VU& Ut, T* buf, int ni, int nj) {
+  const int l = lane_id(), j = tcol<TB>(l);
+  constexpr int E = Tile<T, TB>::EPL;
+  T* colbuf = buf;        // colbuf[j] = element finalised in column j this step
+  T* rowbuf = buf + TB;   // rowbuf[i] = element finalised in row i this step
+  T rinv[E];
+  const T ujj = Ut(j, j);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int i = trow<T, TB>(l, r);
+    rinv[r] = (i < ni && j < nj) ? T(1) / (Lt(i, i) + ujj) : T(0);
+  }
+#pragma unroll 1
+  for (int s = 0; s < 2 * TB - 1; ++s) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = trow<T, TB>(l, r);
+      if (i + j == s) {
+        const T x = c.v[r] * rinv[r];
+        c.v[r] = x;
+        colbuf[j] = x;
+        rowbuf[i] = x;
+      }
+    }
+    wave_fence();
+    const int k = s - j;
+    const T xc = colbuf[j];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = trow<T, TB>(l, r);
+      if (k >= 0 && k < i) c.v[r] -= Lt(i, k) * xc;
+      const int k2 = s - i;
+      if (k2 >= 0 && k2 < j) c.v[r] -= rowbuf[i] * Ut(k2, j);
+    }
+    wave_fence();
+  }
+}
+
+// Upper Cholesky of a diagonal tile held in c (only j >= i is used/valid):
+// unblocked right-looking.  Pivots of rows >= nv are padding (value 1).
+// The first failing pivot (<= 0 or NaN) is reported as base + k + 1 into
+// *info if *info is still 0.
+template <class T, int TB>
+TLA_DI void tile_potf2(Tile<T, TB>& c, T* buf, int nv, int base, int* info) {
+  const int l = lane_id(), j = tcol<TB>(l);
+  constexpr int E = Tile<T, TB>::EPL;
+  T* diag = buf;        // diag[k] = x_kk
+  T* rowk = buf + TB;   // rowk[j] = x_kj of the current k
+#pragma unroll 1
+  for (int k = 0; k < TB; ++k) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = trow<T, TB>(l, r);
+      if (i == k && j == k) {
+        const T p = c.v[r];
+        if (!(p > T(0)) && k < nv && *info == 0) *info = base + k + 1;
+        const T d = sqrt(p);
+        c.v[r] = d;
+        diag[k] = d;
+        rowk[k] = d;
+      }
+    }
+    wave_fence();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = trow<T, TB>(l, r);
+      if (i == k && j > k) {
+        const T x = c.v[r] / diag[k];
+        c.v[r] = x;
+        rowk[j] = x;
+      }
+    }
+    wave_fence();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = trow<T, TB>(l, r);
+      if (i > k && j >= i) c.v[r] -= rowk[i] * rowk[j];
+    }
+    wave_fence();
+  }
+}
+
+// Left solve with the transpose of an upper-triangular diagonal tile:
+// c := Xd^{-T} c  (forward substitution down every column).
+template <class T, int TB, class VX>
+TLA_DI void tile_trsm_ut(Tile<T, TB>& c, const VX& Xd, T* buf) {
+  const int l = lane_id(), j = tcol<TB>(l);
+  constexpr int E = Tile<T, TB>::EPL;
+#pragma unroll 1
+  for (int k = 0; k < TB; ++k) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      if (trow<T, TB>(l, r) == k) {
+        const T y = c.v[r] / Xd(k, k);
+        c.v[r] = y;
+        buf[j] = y;
+      }
+    }
+    wave_fence();
+    const T y = buf[j];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = trow<T, TB>(l, r);
+      if (i > k) c.v[r] -= Xd(k, i) * y;
+    }
+    wave_fence();
+  }
+}
+
+// Right solve with an upper-triangular diagonal tile: c := c Xd^{-1}
+// (substitution along every row, left to right).
+template <class T, int TB, class VX>
+TLA_DI void tile_trsm_right_u(Tile<T, TB>& c, const VX& Xd, T* buf) {
+  const int l = lane_id(), j = tcol<TB>(l);
+  constexpr int E = Tile<T, TB>::EPL;
+#pragma unroll 1
+  for (int k = 0; k < TB; ++k) {
+    if (j == k) {
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const T y = c.v[r] / Xd(k, k);
+        c.v[r] = y;
+        buf[trow<T, TB>(l, r)] = y;
+      }
+    }
+    wave_fence();
+    if (j > k) {
+      const T u = Xd(k, j);
+#pragma unroll
+      for (int r = 0; r < E; ++r) c.v[r] -= buf[trow<T, TB>(l, r)] * u;
+    }
+    wave_fence();
+  }
+}
+
+}  // namespace tla

@@ -1,0 +1,56 @@
+"""The C-ABI library loads without a GPU and exports every entry point that
+include/tla.h declares (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "tla.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"\b(tla_[a-z0-9_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_header_declares_core_entry_points():
+    names = header_functions()
+    for n in ["tla_potrf_batched", "tla_trsyl_batched", "tla_trlyap_batched", "tla_ragged_batched",
+              "tla_create", "tla_destroy", "tla_tune"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1906_08613_amd as tla
+    if not os.path.exists(tla.LIB_PATH):
+        pytest.skip("libtla.so not built")
+    lib = ctypes.CDLL(tla.LIB_PATH)
+    missing = [n for n in header_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_only_queries():
+    import paper_1906_08613_amd as tla
+    if not os.path.exists(tla.LIB_PATH):
+        pytest.skip("libtla.so not built")
+    assert tla.num_candidates("potrf") == 27
+    assert tla.num_candidates("trsyl") == 45
+    assert tla.variant_name("trsyl", 0) == "tile-wavefront"
+    assert tla.lib().tla_status_string(4).decode() == "unsupported"
+    # a null handle is rejected before any device work
+    assert tla.lib().tla_potrf_batched(None, 0, 1, 4, None, None, None, None, None) == tla.E_ARG
+    assert tla.lib().tla_sync(None) == tla.E_ARG
+
+
+def test_product_does_not_touch_oracle():
+    # the product package neither imports nor links the oracle
+    pkg = os.path.join(ROOT, "paper_1906_08613_amd")
+    for dp, _, fs in os.walk(pkg):
+        for f in fs:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                txt = open(os.path.join(dp, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "tla_oracle" not in txt and "liboracle" not in txt, f

@@ -1,0 +1,218 @@
+"""GPU parity of the FP64 path against the CPU oracle, through the C ABI.
+
+Tolerance: the FP64 results must match the oracle to a relative Frobenius
+error of 1e-12 per instance (inputs have condition numbers of about 2, so
+both sides are accurate to a few ulps; 1e-12 leaves margin for the different
+summation orders of the blocked variants).  Backward errors must stay below
+1e-13.  Sizes span one tile, several tiles and ragged tails.
+"""
+import numpy as np
+import pytest
+
+import paper_1906_08613_amd as tla
+from paper_1906_08613_amd import inputs as I
+from tests.gpu_util import rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hd = tla.Handle(0)
+    yield hd
+    hd.close()
+
+
+def all_plans(op):
+    return [tla.candidate(op, i).astuple() for i in range(tla.num_candidates(op))]
+
+
+def run_potrf(h, A, plan=None, prec="f64"):
+    h.set_plan("potrf", prec, plan)
+    dA = tla.to_device_cm(np.triu(A))
+    ops = tla.potrf(h, dA, prec)
+    torch.cuda.synchronize()
+    return np.triu(tla.from_device_cm(dA)), ops.info.cpu().numpy()
+
+
+def run_trsyl(h, L, U, C, plan=None, prec="f64"):
+    h.set_plan("trsyl", prec, plan)
+    dL, dU, dC = tla.to_device_cm(L), tla.to_device_cm(U), tla.to_device_cm(C)
+    ops = tla.trsyl(h, dL, dU, dC, prec)
+    torch.cuda.synchronize()
+    return tla.from_device_cm(dC), ops.info.cpu().numpy()
+
+
+def run_trlyap(h, L, S, plan=None, prec="f64"):
+    h.set_plan("trlyap", prec, plan)
+    dL, dS = tla.to_device_cm(L), tla.to_device_cm(np.tril(S))
+    ops = tla.trlyap(h, dL, dS, prec)
+    torch.cuda.synchronize()
+    return tla.from_device_cm(dS), ops.info.cpu().numpy()
+
+
+SIZES = [1, 3, 8, 15, 16, 17, 31, 40, 64, 65, 100, 127, 128]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_potrf_default_plan(h, orc, n):
+    print(f"potrf n={n}", flush=True)
+    A = I.potrf_problem("gpu-potrf", n, 24)
+    X, info = run_potrf(h, A)
+    Xr, ir = orc.potrf_batch(A)
+    assert np.all(info == 0) and np.all(ir == 0)
+    assert rel_err(X, Xr).max() <= TOL
+    assert orc.eta_potrf_batch(A, X).max() <= 1e-13
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_trsyl_default_plan(h, orc, n):
+    print(f"trsyl n={n}", flush=True)
+    L, U, C = I.trsyl_problem("gpu-trsyl", n, 24)
+    X, info = run_trsyl(h, L, U, C)
+    Xr, ir = orc.trsyl_batch(L, U, C)
+    assert np.all(info == 0)
+    assert rel_err(X, Xr).max() <= TOL
+    assert orc.eta_trsyl_batch(L, U, C, X).max() <= 1e-13
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_trlyap_default_plan(h, orc, n):
+    print(f"trlyap n={n}", flush=True)
+    L, S = I.trlyap_problem("gpu-trlyap", n, 24)
+    X, info = run_trlyap(h, L, S)
+    Xr, ir = orc.trlyap_batch(L, S)
+    assert np.all(info == 0)
+    assert np.array_equal(X, np.swapaxes(X, 1, 2))     # exactly symmetric
+    assert rel_err(X, Xr).max() <= TOL
+    assert orc.eta_trlyap_batch(L, S, X).max() <= 1e-13
+
+
+@pytest.mark.parametrize("n", [21, 64])
+def test_potrf_every_plan(h, orc, n):
+    A = I.potrf_problem("gpu-potrf-plans", n, 8)
+    Xr, _ = orc.potrf_batch(A)
+    for plan in all_plans("potrf"):
+        print(f"potrf n={n} plan={plan}", flush=True)
+        X, info = run_potrf(h, A, plan)
+        assert np.all(info == 0), plan
+        assert rel_err(X, Xr).max() <= TOL, plan
+
+
+@pytest.mark.parametrize("n", [21, 64])
+def test_trsyl_every_plan(h, orc, n):
+    L, U, C = I.trsyl_problem("gpu-trsyl-plans", n, 8)
+    Xr, _ = orc.trsyl_batch(L, U, C)
+    for plan in all_plans("trsyl"):
+        print(f"trsyl n={n} plan={plan}", flush=True)
+        X, info = run_trsyl(h, L, U, C, plan)
+        assert np.all(info == 0), plan
+        assert rel_err(X, Xr).max() <= TOL, plan
+
+
+@pytest.mark.parametrize("n", [21, 64])
+def test_trlyap_every_plan(h, orc, n):
+    L, S = I.trlyap_problem("gpu-trlyap-plans", n, 8)
+    Xr, _ = orc.trlyap_batch(L, S)
+    for plan in all_plans("trlyap"):
+        print(f"trlyap n={n} plan={plan}", flush=True)
+        X, info = run_trlyap(h, L, S, plan)
+        assert np.all(info == 0), plan
+        assert rel_err(X, Xr).max() <= TOL, plan
+
+
+@pytest.mark.parametrize("n", [100, 128])
+def test_large_n_global_coefficients(h, orc, n):
+    # at n > 64 the FP64 Sylvester/Lyapunov kernels read L and U through the caches
+    L, U, C = I.trsyl_problem("gpu-big", n, 6)
+    Xr, _ = orc.trsyl_batch(L, U, C)
+    for plan in [(0, 16, 1, 4), (2, 16, 1, 4), (3, 8, 0, 2)]:
+        X, info = run_trsyl(h, L, U, C, plan)
+        assert np.all(info == 0) and rel_err(X, Xr).max() <= TOL, plan
+    L, S = I.trlyap_problem("gpu-big", n, 6)
+    Zr, _ = orc.trlyap_batch(L, S)
+    for plan in [(0, 16, 1, 4), (2, 16, 1, 2)]:
+        Z, info = run_trlyap(h, L, S, plan)
+        assert np.all(info == 0) and rel_err(Z, Zr).max() <= TOL, plan
+
+
+# ---------------------------------------------------------------- goldens
+def test_golden_cases_on_gpu(h):
+    from tests.golden.load import load
+    g = load("potrf_int3.txt")
+    X, info = run_potrf(h, g["A"][None])
+    assert info[0] == 0 and np.array_equal(X[0], g["X"])
+    g = load("trsyl_dyadic3.txt")
+    X, info = run_trsyl(h, g["L"][None], g["U"][None], g["C"][None])
+    assert info[0] == 0 and np.array_equal(X[0], g["X"])
+    g = load("trlyap_dyadic3.txt")
+    X, info = run_trlyap(h, g["L"][None], g["S"][None])
+    assert info[0] == 0 and np.array_equal(X[0], g["X"])
+
+
+# ----------------------------------------------------------- edge cases
+def test_referenced_triangles_only(h):
+    n, b = 37, 4
+    A = I.potrf_problem("tri-gpu", n, b)
+    host = np.triu(A) + np.tril(np.full((n, n), 7.25), -1)
+    dA = tla.to_device_cm(host)
+    tla.potrf(h, dA)
+    torch.cuda.synchronize()
+    X = tla.from_device_cm(dA)
+    il = np.tril_indices(n, -1)
+    assert np.all(X[:, il[0], il[1]] == 7.25)     # strict lower part untouched
+    # coefficients' unreferenced triangles are never read
+    L, U, C = I.trsyl_problem("tri-gpu", n, b)
+    X1, _ = run_trsyl(h, L + np.triu(np.full((n, n), np.nan), 1), U + np.tril(np.full((n, n), np.nan), -1), C)
+    X2, _ = run_trsyl(h, L, U, C)
+    assert np.array_equal(X1, X2)
+
+
+def test_padded_leading_dimension(h, orc):
+    n, ld, b = 29, 40, 5
+    L, U, C = I.trsyl_problem("ld", n, b)
+    dL, dU, dC = tla.to_device_cm(L, ld=ld), tla.to_device_cm(U, ld=ld), tla.to_device_cm(C, ld=ld)
+    h.set_plan("trsyl", "f64", None)
+    ops = tla.trsyl(h, dL, dU, dC)
+    torch.cuda.synchronize()
+    Xr, _ = orc.trsyl_batch(L, U, C)
+    assert rel_err(tla.from_device_cm(dC, n), Xr).max() <= TOL
+    assert np.all(dC.cpu().numpy()[:, :, n:] == 0)   # padding rows untouched
+
+
+def test_info_codes(h):
+    n = 6
+    # non-SPD: leading minor of order 4 fails; n = 0 quick return; bad n / ld
+    A = np.stack([np.eye(n)] * 4)
+    A[0, 3, 3] = -1.0
+    dA = tla.to_device_cm(A)
+    ops = tla.Operands(n, dA)
+    nn = torch.tensor([n, 0, n + 5, n], dtype=torch.int32, device="cuda")
+    ld = torch.tensor([n, n, n, n - 1], dtype=torch.int32, device="cuda")
+    h.potrf_batched("f64", 4, n, nn, ops.ptrs[0], ld, ops.info)
+    torch.cuda.synchronize()
+    assert ops.info.cpu().tolist() == [4, 0, -1, -2]
+    # zero denominators l_ii + u_jj
+    L = np.eye(n)[None].copy()
+    U = np.eye(n)[None].copy()
+    L[0, 2, 2] = -1.0
+    X, info = run_trsyl(h, L, U, np.ones((1, n, n)))
+    assert info[0] == 1 + 2
+    L = np.eye(n)[None].copy()
+    L[0, 4, 4] = -1.0
+    X, info = run_trlyap(h, L, np.ones((1, n, n)))
+    assert info[0] == 1 + 4 + 0 * n
+
+
+def test_host_argument_errors(h):
+    with pytest.raises(tla.TlaError):
+        h.potrf_batched("f64", -1, 4, None, None, None, None)
+    with pytest.raises(tla.TlaError):
+        h.potrf_batched("f64", 4, 4, None, None, None, None)
+    # batch 0 is a no-op
+    h.potrf_batched("f64", 0, 4, None, None, None, None)
