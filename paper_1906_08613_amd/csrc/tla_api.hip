@@ -173,7 +173,9 @@ tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& 
     else if (op == TLA_TRSYL) fn = trsyl_f64_kernel(p.variant, te, nwi, lu);
     else fn = trlyap_f64_kernel(p.variant, te, nwi, lu);
   } else {
-    return TLA_E_UNSUPPORTED;
+    if (op == TLA_POTRF) fn = potrf_mixed_kernel(prec, p.variant, te, nwi);
+    else if (op == TLA_TRSYL) fn = trsyl_mixed_kernel(prec, p.variant, te, nwi, lu);
+    else fn = trlyap_mixed_kernel(prec, p.variant, te, nwi, lu);
   }
   if (!fn) return TLA_E_UNSUPPORTED;
   if (getenv("TLA_LOG"))

@@ -15,8 +15,9 @@ namespace tla {
 // ----------------------------------------------------------- global views
 // Read-only view of a caller matrix in global memory, with the coordinates
 // of the underlying column-major matrix.  Entries outside n x n or outside
-// the referenced triangle (tri < 0: lower, tri > 0: upper) read as zero, so
-// padded tiles need no special casing.
+// the referenced triangle (tri -1: lower, +1: upper) read as zero, so padded
+// tiles need no special casing; tri +2 / -2 read a symmetric matrix from its
+// upper / lower triangle.
 template <class T>
 struct GView {
   const double* p;
@@ -26,7 +27,12 @@ struct GView {
   TLA_DI T operator()(int i, int j) const {
     const int r = tr ? r0 + j : r0 + i;
     const int c = tr ? c0 + i : c0 + j;
-    const bool ok = r < n && c < n && (tri == 0 || (tri < 0 ? r >= c : r <= c));
+    if (r >= n || c >= n) return T(0);
+    if (tri == 2 || tri == -2) {  // symmetric, stored in the upper (2) or lower (-2) triangle
+      const bool swap = tri == 2 ? r > c : r < c;
+      return swap ? T(p[c + (size_t)r * ld]) : T(p[r + (size_t)c * ld]);
+    }
+    const bool ok = tri == 0 || (tri < 0 ? r >= c : r <= c);
     return ok ? T(p[r + (size_t)c * ld]) : T(0);
   }
   TLA_DI GView sub(int i0, int j0) const {
@@ -42,25 +48,48 @@ TLA_DI GView<T> gview(const double* p, int ld, int n, int tri) { return GView<T>
 // ------------------------------------------------------ ingest / egress
 // Copies the n x n global matrix into the np x np LDS matrix (ld = ldw),
 // keeping the part selected by `part` and writing `pad` on the padded
-// diagonal and zero elsewhere.  part: 0 full, -1 lower (i >= j), +1 upper,
-// 2 lower mirrored into both halves (symmetric input given by its lower
-// triangle).  Columns are spread over waves, rows over lanes (coalesced).
+// diagonal and zero elsewhere.  part: 0 full, -1 lower (i >= j), +1 upper.
+// Rows go to lanes (coalesced column reads), columns to waves; U columns are
+// loaded before any is stored so that their latencies overlap.  Returns this
+// thread's share of the squared Frobenius norm of the kept part, counting
+// off-diagonal entries twice when `sym` (a symmetric matrix given by one
+// triangle).
 template <class T, int NW>
-TLA_DI void ingest(T* W, int ldw, int np, const double* G, int ldg, int n, int part, T pad) {
+TLA_DI double ingest(T* W, int ldw, int np, const double* G, int ldg, int n, int part, T pad, bool sym = false) {
+  constexpr int U = 8;
   const int w = wave_id(), l = lane_id();
-  for (int j = w; j < np; j += NW) {
-    for (int i = l; i < np; i += 64) {
-      T v;
-      if (i < n && j < n) {
-        if (part == 0) v = T(G[i + (size_t)j * ldg]);
-        else if (part == -1) v = i >= j ? T(G[i + (size_t)j * ldg]) : T(0);
-        else if (part == 1) v = i <= j ? T(G[i + (size_t)j * ldg]) : T(0);
-        else v = i >= j ? T(G[i + (size_t)j * ldg]) : T(G[j + (size_t)i * ldg]);
-      } else {
-        v = (i == j) ? pad : T(0);
+  double ss = 0.0;
+  for (int i0 = 0; i0 < np; i0 += 64) {
+    const int i = i0 + l;
+    for (int jb = w; jb < np; jb += NW * U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = jb + u * NW;
+        const bool keep = i < n && j < n && (part == 0 || (part < 0 ? i >= j : i <= j));
+        v[u] = keep ? G[i + (size_t)j * ldg] : 0.0;
       }
-      W[i + j * ldw] = v;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = jb + u * NW;
+        if (i < np && j < np) {
+          const bool inside = i < n && j < n;
+          W[i + j * ldw] = inside ? T(v[u]) : (i == j ? pad : T(0));
+          ss += (sym && i != j ? 2.0 : 1.0) * v[u] * v[u];
+        }
+      }
     }
+  }
+  return ss;
+}
+
+// Mirrors the lower triangle of an np x np LDS matrix into its upper triangle
+// (call between barriers).
+template <class T>
+TLA_DI void mirror_lower(T* W, int ldw, int np) {
+  for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+    const int j = e / np, i = e - j * np;
+    if (i < j) W[i + j * ldw] = W[j + i * ldw];
   }
 }
 
@@ -192,8 +221,10 @@ __global__ __launch_bounds__(NW * 64) void k_trlyap_f64(KArgs g) {
   double* wb = LU_LDS ? Ls + mat : Ls;
   int* s_info = reinterpret_cast<int*>(wb + NW * 4 * TB);
   if (threadIdx.x == 0) *s_info = INT_MAX;
-  ingest<double, NW>(X, ld, np, g.c[b], g.ldc[b], n, 2, 0.0);
+  ingest<double, NW>(X, ld, np, g.c[b], g.ldc[b], n, -1, 0.0);
   if constexpr (LU_LDS) ingest<double, NW>(Ls, ld, np, g.a[b], g.lda[b], n, -1, 0.0);
+  __syncthreads();
+  mirror_lower(X, ld, np);
   __syncthreads();
   Ctx<double> cx{n, nt, wb + wave_id() * 4 * TB, s_info};
   if constexpr (LU_LDS) {

@@ -1,0 +1,468 @@
+// Mixed precision with FP64 refinement, one workgroup per instance.
+//
+// The paper computes in double precision only.  Here each instance is
+// first solved in FP32 (tile updates on the FP32, FP16 or BF16 matrix cores
+// with FP32 accumulation, diagonal tiles in FP32 vector arithmetic), then
+// refined in FP64 until the backward error eta drops below tau:
+//   Sylvester / Lyapunov (classical refinement):
+//     R = C - (L X + X U) in FP64, eta, D = solve_lo(R), X += D in FP64.
+//   Cholesky (Newton correction of the factor): with R = A - X^T X,
+//     linearising (X+E)^T (X+E) = A gives X^T E + E^T X = R; E = F X with F
+//     upper triangular solves it when F + F^T = X^{-T} R X^{-1} = M, so
+//     F = triu(M) with its diagonal halved and X += F X.
+// Only the residual, the correction accumulation and the fallback run in
+// FP64.  Refinement stops with FALLBACK when eta_k > eta_{k-1}/2 (stall) or
+// after max_iter corrections, with BREAKDOWN when the low-precision solve
+// meets a zero pivot/denominator or produces a non-finite value; both then
+// solve the instance again by the FP64 kernel code.  Input and output are
+// FP64; the FP64 solution lives in LDS (Xd) next to the FP32 work matrix (W).
+#pragma once
+#include "tla_kernels.hpp"
+
+namespace tla {
+
+template <int NW>
+TLA_DI double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if (lane_id() == 0) red[wave_id()] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s += red[w];
+  return s;
+}
+
+template <int NW>
+TLA_DI int block_or(int v, int* red) {
+  __syncthreads();
+  if (threadIdx.x == 0) *red = 0;
+  __syncthreads();
+  if (v) atomicOr(red, v);
+  __syncthreads();
+  return *red;
+}
+
+// Which FP64 tile engine the residual and the fallback use.
+template <int TB>
+struct F64Eng { static constexpr int value = TB == 16 ? ENG_MFMA : ENG_VALU; };
+
+// Convergence bookkeeping shared by the three operations.
+struct RefineState {
+  double eta, prev;
+  int it, flags;
+};
+
+// Decide after a residual: returns true when the loop must stop.
+TLA_DI bool refine_decide(RefineState& st, double eta, double tau, int max_iter) {
+  st.eta = eta;
+  if (eta <= tau) { st.flags |= TLA_STAT_CONVERGED; return true; }
+  if (!(eta == eta) || st.it >= max_iter || !(eta <= 0.5 * st.prev)) { st.flags |= TLA_STAT_FALLBACK; return true; }
+  st.prev = eta;
+  return false;
+}
+
+TLA_DI void write_stat(const KArgs& g, int b, const RefineState& st) {
+  if (threadIdx.x == 0 && g.stat) {
+    g.stat[b].iters = st.it;
+    g.stat[b].flags = st.flags;
+    g.stat[b].eta = st.eta;
+  }
+}
+
+// LDS carve-up of the mixed kernels: Xd (FP64), W (FP32), aux (FP32:
+// coefficients or the FP32 factor), scratch, reduction cells.
+struct MixedLds {
+  double* Xd;
+  float* W;
+  float* A1;
+  float* A2;
+  float* wb;
+  double* red;
+  int* ired;
+  int* info;
+};
+
+template <int TB, int NW>
+TLA_DI MixedLds carve(unsigned char* smem, int ntmax, int naux) {
+  const size_t np = (size_t)ntmax * TB, mat = np * (np + 1);
+  MixedLds m;
+  m.Xd = reinterpret_cast<double*>(smem);
+  m.W = reinterpret_cast<float*>(m.Xd + mat);
+  m.A1 = m.W + mat;
+  m.A2 = m.A1 + (naux >= 1 ? mat : 0);
+  float* after = m.A2 + (naux >= 2 ? mat : 0);
+  m.wb = after;
+  m.red = reinterpret_cast<double*>(m.wb + NW * 4 * TB + 4);
+  m.red = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(m.red) + 7) & ~uintptr_t(7));
+  m.ired = reinterpret_cast<int*>(m.red + NW + 1);
+  m.info = m.ired + 1;
+  return m;
+}
+
+// float view of an FP64 global matrix (coefficients read through the caches)
+template <class T>
+TLA_DI bool all_finite_lds(const T* W, int ldw, int n) {
+  bool ok = true;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int j = e / n, i = e - j * n;
+    const T v = W[i + j * ldw];
+    ok = ok && (v - v == T(0));
+  }
+  return ok;
+}
+
+// ===================================================== Sylvester, mixed
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS>
+__global__ __launch_bounds__(NW * 64) void k_trsyl_mixed(KArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x;
+  int n;
+  if (!validate(g, b, n)) return;
+  const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
+  const MixedLds m = carve<TB, NW>(smem, g.ntmax, LU_LDS ? 2 : 0);
+  const double* Lg = g.a[b];
+  const double* Ug = g.b[b];
+  double* Cg = g.c[b];
+  const int ldl = g.lda[b], ldu = g.ldb[b], ldc = g.ldc[b];
+  const GView<double> L64 = gview<double>(Lg, ldl, n, -1);
+  const GView<double> U64 = gview<double>(Ug, ldu, n, +1);
+  const GView<double> C64 = gview<double>(Cg, ldc, n, 0);
+  constexpr int E64 = F64Eng<TB>::value;
+  if (threadIdx.x == 0) *m.info = INT_MAX;
+  RefineState st{INFINITY, INFINITY, 0, 0};
+
+  double sc = ingest<float, NW>(m.W, ld, np, Cg, ldc, n, 0, 0.0f);
+  double sl = 0.0, su = 0.0;
+  if constexpr (LU_LDS) {
+    sl = ingest<float, NW>(m.A1, ld, np, Lg, ldl, n, -1, 0.0f);
+    su = ingest<float, NW>(m.A2, ld, np, Ug, ldu, n, +1, 0.0f);
+  } else {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int j = e / n, i = e - j * n;
+      const double lv = L64(i, j), uv = U64(i, j);
+      sl += lv * lv;
+      su += uv * uv;
+    }
+  }
+  const double nc = sqrt(block_sum<NW>(sc, m.red));
+  const double nl = sqrt(block_sum<NW>(sl, m.red));
+  const double nu = sqrt(block_sum<NW>(su, m.red));
+  int bad = (nc - nc != 0.0 || nl - nl != 0.0 || nu - nu != 0.0) ? TLA_STAT_NONFINITE : 0;
+  // exact zero denominators (FP64) decide info; FP32 ones only force the FP64 path
+  scan_zero_denoms(L64, U64, n, false, m.info);
+  int lo_zero = 0;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int j = e / n, i = e - j * n;
+    if (float(L64(i, i)) + float(U64(j, j)) == 0.0f) lo_zero = TLA_STAT_BREAKDOWN;
+  }
+  bad |= block_or<NW>(lo_zero | bad, m.ired);
+  st.flags |= bad;
+  const int info0 = *m.info == INT_MAX ? 0 : *m.info;
+  Ctx<float> cx{n, nt, m.wb + wave_id() * 4 * TB, m.info};
+  if (info0 == 0 && !bad) {
+    // low-precision solve of the full system
+    if constexpr (LU_LDS) trsyl_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), colmajor(m.A1, ld), colmajor(m.A2, ld), cx);
+    else trsyl_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), gview<float>(Lg, ldl, n, -1), gview<float>(Ug, ldu, n, +1), cx);
+    __syncthreads();
+    if (block_or<NW>(all_finite_lds(m.W, ld, n) ? 0 : 1, m.ired)) st.flags |= TLA_STAT_BREAKDOWN;
+    if (!(st.flags & TLA_STAT_BREAKDOWN)) {
+      for (int e = threadIdx.x; e < np * ld; e += blockDim.x) m.Xd[e] = double(m.W[e]);
+      __syncthreads();
+      for (;;) {
+        // R = C - L Xd - Xd U (FP64), into W; squared norms of R and Xd
+        double sr = 0.0, sx = 0.0;
+        const View<double> Xv = colmajor(m.Xd, ld);
+        for (int t = wave_id(); t < nt * nt; t += NW) {
+          const int I = t / nt, J = t - I * nt;
+          Tile<double, TB> c, x;
+          tload(c, C64.sub(I * TB, J * TB));
+          tload(x, Xv.sub(I * TB, J * TB));
+          for (int K = 0; K <= I; ++K) Gemm<double, TB, E64>::sub(c, L64.sub(I * TB, K * TB), Xv.sub(K * TB, J * TB));
+          for (int K = 0; K <= J; ++K) Gemm<double, TB, E64>::sub(c, Xv.sub(I * TB, K * TB), U64.sub(K * TB, J * TB));
+          const int l = lane_id(), j = tcol<TB>(l);
+#pragma unroll
+          for (int r = 0; r < Tile<double, TB>::EPL; ++r) {
+            const int i = trow<double, TB>(l, r);
+            m.W[(I * TB + i) + (J * TB + j) * ld] = float(c.v[r]);
+            sr += c.v[r] * c.v[r];
+            sx += x.v[r] * x.v[r];
+          }
+        }
+        const double nr = sqrt(block_sum<NW>(sr, m.red));
+        const double nx = sqrt(block_sum<NW>(sx, m.red));
+        const double eta = nr / ((nl + nu) * nx + nc);
+        if (refine_decide(st, eta, g.tau, g.max_iter)) break;
+        __syncthreads();
+        if constexpr (LU_LDS) trsyl_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), colmajor(m.A1, ld), colmajor(m.A2, ld), cx);
+        else trsyl_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), gview<float>(Lg, ldl, n, -1), gview<float>(Ug, ldu, n, +1), cx);
+        __syncthreads();
+        for (int e = threadIdx.x; e < np * ld; e += blockDim.x) m.Xd[e] += double(m.W[e]);
+        ++st.it;
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+  if (info0 == 0 && !(st.flags & TLA_STAT_CONVERGED)) {
+    // FP64 solve of the instance (fallback or breakdown)
+    ingest<double, NW>(m.Xd, ld, np, Cg, ldc, n, 0, 0.0);
+    __syncthreads();
+    Ctx<double> cd{n, nt, reinterpret_cast<double*>(m.W), m.info};
+    cd.wbuf = reinterpret_cast<double*>(m.W) + wave_id() * 4 * TB;
+    constexpr int ENG64 = ENG == ENG_VALU ? ENG_VALU : E64;
+    trsyl_blocked<double, TB, ENG64, NW, VAR>(colmajor(m.Xd, ld), L64, U64, cd);
+    __syncthreads();
+  }
+  if (info0 == 0) egress<double, NW>(Cg, ldc, n, m.Xd, ld, 0);
+  if (threadIdx.x == 0) g.info[b] = info0;
+  write_stat(g, b, st);
+}
+
+// ===================================================== Lyapunov, mixed
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS>
+__global__ __launch_bounds__(NW * 64) void k_trlyap_mixed(KArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x;
+  int n;
+  if (!validate(g, b, n)) return;
+  const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
+  const MixedLds m = carve<TB, NW>(smem, g.ntmax, LU_LDS ? 1 : 0);
+  const double* Lg = g.a[b];
+  double* Sg = g.c[b];
+  const int ldl = g.lda[b], lds = g.ldc[b];
+  const GView<double> L64 = gview<double>(Lg, ldl, n, -1);
+  const GView<double> S64 = gview<double>(Sg, lds, n, -2);
+  constexpr int E64 = F64Eng<TB>::value;
+  if (threadIdx.x == 0) *m.info = INT_MAX;
+  RefineState st{INFINITY, INFINITY, 0, 0};
+
+  double ss = ingest<float, NW>(m.W, ld, np, Sg, lds, n, -1, 0.0f, true);
+  double sl = 0.0;
+  if constexpr (LU_LDS) {
+    sl = ingest<float, NW>(m.A1, ld, np, Lg, ldl, n, -1, 0.0f);
+  } else {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int j = e / n, i = e - j * n;
+      const double lv = L64(i, j);
+      sl += lv * lv;
+    }
+  }
+  __syncthreads();
+  mirror_lower(m.W, ld, np);
+  const double ns = sqrt(block_sum<NW>(ss, m.red));
+  const double nl = sqrt(block_sum<NW>(sl, m.red));
+  int bad = (ns - ns != 0.0 || nl - nl != 0.0) ? TLA_STAT_NONFINITE : 0;
+  scan_zero_denoms(L64, L64, n, true, m.info);
+  int lo_zero = 0;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int j = e / n, i = e - j * n;
+    if (i >= j && float(L64(i, i)) + float(L64(j, j)) == 0.0f) lo_zero = TLA_STAT_BREAKDOWN;
+  }
+  bad |= block_or<NW>(lo_zero | bad, m.ired);
+  st.flags |= bad;
+  const int info0 = *m.info == INT_MAX ? 0 : *m.info;
+  Ctx<float> cx{n, nt, m.wb + wave_id() * 4 * TB, m.info};
+  if (info0 == 0 && !bad) {
+    if constexpr (LU_LDS) trlyap_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), colmajor(m.A1, ld), cx);
+    else trlyap_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), gview<float>(Lg, ldl, n, -1), cx);
+    __syncthreads();
+    mirror_lower(m.W, ld, np);
+    __syncthreads();
+    if (block_or<NW>(all_finite_lds(m.W, ld, n) ? 0 : 1, m.ired)) st.flags |= TLA_STAT_BREAKDOWN;
+    if (!(st.flags & TLA_STAT_BREAKDOWN)) {
+      for (int e = threadIdx.x; e < np * ld; e += blockDim.x) m.Xd[e] = double(m.W[e]);
+      __syncthreads();
+      for (;;) {
+        // R = S - L Xd - Xd L^T on the lower tiles (Xd is kept symmetric)
+        double sr = 0.0, sx = 0.0;
+        const View<double> Xv = colmajor(m.Xd, ld);
+        for (int t = wave_id(); t < nt * nt; t += NW) {
+          const int I = t / nt, J = t - I * nt;
+          if (I < J) continue;
+          Tile<double, TB> c, x;
+          tload(c, S64.sub(I * TB, J * TB));
+          tload(x, Xv.sub(I * TB, J * TB));
+          for (int K = 0; K <= I; ++K) Gemm<double, TB, E64>::sub(c, L64.sub(I * TB, K * TB), Xv.sub(K * TB, J * TB));
+          for (int K = 0; K <= J; ++K) Gemm<double, TB, E64>::sub(c, Xv.sub(I * TB, K * TB), L64.sub(J * TB, K * TB).t());
+          const double wgt = I == J ? 1.0 : 2.0;
+          const int l = lane_id(), j = tcol<TB>(l);
+#pragma unroll
+          for (int r = 0; r < Tile<double, TB>::EPL; ++r) {
+            const int i = trow<double, TB>(l, r);
+            m.W[(I * TB + i) + (J * TB + j) * ld] = float(c.v[r]);
+            sr += wgt * c.v[r] * c.v[r];
+            sx += wgt * x.v[r] * x.v[r];
+          }
+        }
+        const double nr = sqrt(block_sum<NW>(sr, m.red));
+        const double nx = sqrt(block_sum<NW>(sx, m.red));
+        const double eta = nr / (2.0 * nl * nx + ns);
+        if (refine_decide(st, eta, g.tau, g.max_iter)) break;
+        __syncthreads();
+        if constexpr (LU_LDS) trlyap_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), colmajor(m.A1, ld), cx);
+        else trlyap_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), gview<float>(Lg, ldl, n, -1), cx);
+        __syncthreads();
+        // Xd += D on the lower triangle, then keep Xd symmetric
+        for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+          const int j = e / np, i = e - j * np;
+          if (i >= j) m.Xd[i + j * ld] += double(m.W[i + j * ld]);
+        }
+        __syncthreads();
+        mirror_lower(m.Xd, ld, np);
+        ++st.it;
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+  if (info0 == 0 && !(st.flags & TLA_STAT_CONVERGED)) {
+    ingest<double, NW>(m.Xd, ld, np, Sg, lds, n, -1, 0.0);
+    __syncthreads();
+    mirror_lower(m.Xd, ld, np);
+    __syncthreads();
+    Ctx<double> cd{n, nt, reinterpret_cast<double*>(m.W) + wave_id() * 4 * TB, m.info};
+    constexpr int ENG64 = ENG == ENG_VALU ? ENG_VALU : E64;
+    trlyap_blocked<double, TB, ENG64, NW, VAR>(colmajor(m.Xd, ld), L64, cd);
+    __syncthreads();
+  }
+  if (info0 == 0) egress<double, NW>(Sg, lds, n, m.Xd, ld, 2);
+  if (threadIdx.x == 0) g.info[b] = info0;
+  write_stat(g, b, st);
+}
+
+// ====================================================== Cholesky, mixed
+// Tile solves of the Newton correction, FP32 (X32 upper factor in aux):
+//   M1 = X^{-T} R   column tile by column tile (forward substitution down)
+//   M  = M1 X^{-1}  row tile by row tile (substitution to the right)
+template <class T, int TB, int ENG, int NW>
+TLA_DI void newton_correction(const View<T>& Wv, const View<T>& Xv, const View<double>& Xd, int nt, T* wbuf) {
+  typedef Gemm<T, TB, ENG> G;
+  const int w = wave_id();
+  for (int J = w; J < nt; J += NW) {
+    for (int I = 0; I < nt; ++I) {
+      Tile<T, TB> c;
+      tload(c, Wv.sub(I * TB, J * TB));
+      for (int K = 0; K < I; ++K) G::sub(c, Xv.sub(K * TB, I * TB).t(), Wv.sub(K * TB, J * TB));
+      tile_trsm_ut<T, TB>(c, Xv.sub(I * TB, I * TB), wbuf);
+      tstore(c, Wv.sub(I * TB, J * TB));
+    }
+  }
+  __syncthreads();
+  for (int I = w; I < nt; I += NW) {
+    for (int J = 0; J < nt; ++J) {
+      Tile<T, TB> c;
+      tload(c, Wv.sub(I * TB, J * TB));
+      for (int K = 0; K < J; ++K) G::sub(c, Wv.sub(I * TB, K * TB), Xv.sub(K * TB, J * TB));
+      tile_trsm_right_u<T, TB>(c, Xv.sub(J * TB, J * TB), wbuf);
+      tstore(c, Wv.sub(I * TB, J * TB));
+    }
+  }
+  __syncthreads();
+  // F = triu(M), diagonal halved (in place on the diagonal tiles' elements)
+  for (int e = threadIdx.x; e < nt * TB * nt * TB; e += blockDim.x) {
+    const int np = nt * TB;
+    const int j = e / np, i = e - j * np;
+    if (i > j) Wv.at(i, j) = T(0);
+    else if (i == j) Wv.at(i, j) = T(0.5) * Wv(i, j);
+  }
+  __syncthreads();
+  // E = F X on the upper tiles; Xd += E
+  for (int t = w; t < nt * nt; t += NW) {
+    const int I = t / nt, J = t - I * nt;
+    if (I > J) continue;
+    Tile<T, TB> c;
+    tzero(c);
+    for (int K = I; K <= J; ++K) G::sub(c, Wv.sub(I * TB, K * TB), Xv.sub(K * TB, J * TB));
+    const int l = lane_id(), j = tcol<TB>(l);
+#pragma unroll
+    for (int r = 0; r < Tile<T, TB>::EPL; ++r) {
+      const int i = trow<T, TB>(l, r);
+      if (I * TB + i <= J * TB + j) Xd.at(I * TB + i, J * TB + j) -= double(c.v[r]);  // c holds -E
+    }
+  }
+}
+
+template <int TB, int ENG, int NW, int VAR>
+__global__ __launch_bounds__(NW * 64) void k_potrf_mixed(KArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x;
+  int n;
+  if (!validate(g, b, n)) return;
+  const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
+  const MixedLds m = carve<TB, NW>(smem, g.ntmax, 1);
+  double* Ag = g.c[b];
+  const int lda = g.ldc[b];
+  const GView<double> A64 = gview<double>(Ag, lda, n, 2);
+  constexpr int E64 = F64Eng<TB>::value;
+  if (threadIdx.x == 0) *m.info = 0;
+  RefineState st{INFINITY, INFINITY, 0, 0};
+
+  const double na = sqrt(block_sum<NW>(ingest<float, NW>(m.W, ld, np, Ag, lda, n, +1, 1.0f, true), m.red));
+  int bad = (na - na != 0.0) ? TLA_STAT_NONFINITE : 0;
+  Ctx<float> cx{n, nt, m.wb + wave_id() * 4 * TB, m.info};
+  if (!bad) {
+    potrf_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), cx);
+    __syncthreads();
+    if (*m.info != 0 || block_or<NW>(all_finite_lds(m.W, ld, n) ? 0 : 1, m.ired)) bad |= TLA_STAT_BREAKDOWN;
+  }
+  st.flags |= bad;
+  if (!bad) {
+    for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+      const int j = e / np, i = e - j * np;
+      m.Xd[i + j * ld] = (i <= j && j < n) ? double(m.W[i + j * ld]) : 0.0;
+    }
+    __syncthreads();
+    const View<double> Xv = colmajor(m.Xd, ld);
+    for (;;) {
+      // R = A - Xd^T Xd, symmetric: upper tiles computed, mirrored into W
+      double sr = 0.0;
+      for (int t = wave_id(); t < nt * nt; t += NW) {
+        const int I = t / nt, J = t - I * nt;
+        if (I > J) continue;
+        Tile<double, TB> c;
+        tload(c, A64.sub(I * TB, J * TB));
+        for (int K = 0; K <= I; ++K) Gemm<double, TB, E64>::sub(c, Xv.sub(K * TB, I * TB).t(), Xv.sub(K * TB, J * TB));
+        const double wgt = I == J ? 1.0 : 2.0;
+        const int l = lane_id(), j = tcol<TB>(l);
+#pragma unroll
+        for (int r = 0; r < Tile<double, TB>::EPL; ++r) {
+          const int i = trow<double, TB>(l, r);
+          const float v = float(c.v[r]);
+          m.W[(I * TB + i) + (J * TB + j) * ld] = v;
+          m.W[(J * TB + j) + (I * TB + i) * ld] = v;
+          sr += wgt * c.v[r] * c.v[r];
+        }
+      }
+      const double eta = sqrt(block_sum<NW>(sr, m.red)) / na;
+      if (refine_decide(st, eta, g.tau, g.max_iter)) break;
+      // FP32 copy of the factor (padding: identity) for the correction solves
+      for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+        const int j = e / np, i = e - j * np;
+        m.A1[i + j * ld] = i < n && j < n ? float(m.Xd[i + j * ld]) : (i == j ? 1.0f : 0.0f);
+      }
+      __syncthreads();
+      newton_correction<float, TB, ENG, NW>(colmajor(m.W, ld), colmajor(m.A1, ld), Xv, nt, m.wb + wave_id() * 4 * TB);
+      ++st.it;
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  int info0 = 0;
+  if (!(st.flags & TLA_STAT_CONVERGED)) {
+    if (threadIdx.x == 0) *m.info = 0;
+    ingest<double, NW>(m.Xd, ld, np, Ag, lda, n, +1, 1.0);
+    __syncthreads();
+    Ctx<double> cd{n, nt, reinterpret_cast<double*>(m.W) + wave_id() * 4 * TB, m.info};
+    constexpr int ENG64 = ENG == ENG_VALU ? ENG_VALU : E64;
+    potrf_blocked<double, TB, ENG64, NW, VAR>(colmajor(m.Xd, ld), cd);
+    __syncthreads();
+    info0 = *m.info;
+  }
+  egress<double, NW>(Ag, lda, n, m.Xd, ld, 1);
+  if (threadIdx.x == 0) g.info[b] = info0;
+  write_stat(g, b, st);
+}
+
+}  // namespace tla

@@ -15,3 +15,12 @@ KFn potrf_f64_kernel(int var, int te, int nwi);
 KFn trsyl_f64_kernel(int var, int te, int nwi, bool lu_lds);
 KFn trlyap_f64_kernel(int var, int te, int nwi, bool lu_lds);
 }  // namespace tla
+
+namespace tla {
+// Mixed-precision kernels.  te 0/1 run FP32 vector-ALU tile updates; te 2
+// runs them on the matrix cores in the input type named by prec
+// (TLA_MIXED_F32: FP32, TLA_MIXED_F16: FP16, TLA_MIXED_BF16: BF16).
+KFn potrf_mixed_kernel(int prec, int var, int te, int nwi);
+KFn trsyl_mixed_kernel(int prec, int var, int te, int nwi, bool lu_lds);
+KFn trlyap_mixed_kernel(int prec, int var, int te, int nwi, bool lu_lds);
+}  // namespace tla
