@@ -138,54 +138,112 @@ extern "C" tla_status tla_set_refine(tla_handle h, double tau, int max_iter) {
 namespace tla {
 
 // LDS bytes for one instance of `op` with ntmax tiles per dimension.
-size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, bool lu_lds) {
+// FP64 kernels, placement 0: coefficients and X in LDS, 1: X only.
+// Mixed kernels: FP32 work matrix W (+ FP32 coefficients / factor copy) and
+// the FP64 solution (placement < last) in LDS; see tla_registry.h.
+size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int pl) {
   const size_t np = (size_t)ntmax * tb;
   const size_t mat8 = np * (np + 1) * 8, mat4 = np * (np + 1) * 4;
-  const size_t scr = (size_t)nw * 4 * tb * 8 + 16;
+  const size_t scr = (size_t)nw * 4 * tb * 8 + 16 + 8 * (nw + 4);
   if (prec == TLA_F64) {
     if (op == TLA_POTRF) return mat8 + scr;
-    if (op == TLA_TRSYL) return mat8 * (lu_lds ? 3 : 1) + scr;
-    return mat8 * (lu_lds ? 2 : 1) + scr;
+    if (op == TLA_TRSYL) return mat8 * (pl == 0 ? 3 : 1) + scr;
+    return mat8 * (pl == 0 ? 2 : 1) + scr;
   }
-  // mixed: FP32 work matrix + FP64 solution + FP32 coefficients (if staged)
-  if (op == TLA_POTRF) return mat8 + 2 * mat4 + scr;
-  if (op == TLA_TRSYL) return mat8 + mat4 * (lu_lds ? 3 : 1) + scr;
-  return mat8 + mat4 * (lu_lds ? 2 : 1) + scr;
+  if (op == TLA_POTRF) return (pl == 0 ? mat8 : 0) + 2 * mat4 + scr;
+  const size_t coef = pl == 0 ? (op == TLA_TRSYL ? 2 : 1) * mat4 : 0;
+  return (pl == 2 ? 0 : mat8) + mat4 + coef + scr;
+}
+
+static tla_status ensure_buffers(tla_ctx* h, size_t work_bytes, int batch) {
+  if (work_bytes > h->work_bytes) {
+    if (h->work) {
+      hipStreamSynchronize(h->stream);
+      hipFree(h->work);
+      h->work = nullptr;
+      h->work_bytes = 0;
+    }
+    if (hipMalloc(&h->work, work_bytes) != hipSuccess) return TLA_E_NOMEM;
+    h->work_bytes = work_bytes;
+  }
+  if ((size_t)batch > h->stat_cap) {
+    if (h->stat_buf) {
+      hipStreamSynchronize(h->stream);
+      hipFree(h->stat_buf);
+      h->stat_buf = nullptr;
+      h->stat_cap = 0;
+    }
+    if (hipMalloc(&h->stat_buf, (size_t)batch * sizeof(tla_stat)) != hipSuccess) return TLA_E_NOMEM;
+    h->stat_cap = batch;
+  }
+  return TLA_OK;
+}
+
+static KFn kernel_for(int op, int prec, const tla_plan& p, int pl) {
+  const int te = te_index(p.tile, p.engine), nwi = nw_index(p.waves);
+  if (prec == TLA_F64) {
+    if (op == TLA_POTRF) return potrf_f64_kernel(p.variant, te, nwi);
+    if (op == TLA_TRSYL) return trsyl_f64_kernel(p.variant, te, nwi, pl == 0);
+    return trlyap_f64_kernel(p.variant, te, nwi, pl == 0);
+  }
+  if (op == TLA_POTRF) return potrf_mixed_kernel(prec, p.variant, te, nwi, pl == 0 ? 0 : 1);
+  if (op == TLA_TRSYL) return trsyl_mixed_kernel(prec, p.variant, te, nwi, pl);
+  return trlyap_mixed_kernel(prec, p.variant, te, nwi, pl);
+}
+
+// First placement whose LDS fits: returns -1 when none does.
+int choose_placement(tla_ctx* h, int op, int prec, const tla_plan& p, int ntmax, size_t* lds) {
+  const int last = prec == TLA_F64 ? (op == TLA_POTRF ? 0 : 1) : (op == TLA_POTRF ? 2 : 2);
+  for (int pl = 0; pl <= last; ++pl) {
+    if (prec != TLA_F64 && op == TLA_POTRF && pl == 1) continue;
+    const size_t b = lds_bytes(op, prec, p.tile, p.waves, ntmax, pl);
+    if (b <= (size_t)h->lds_limit) { *lds = b; return pl; }
+  }
+  return -1;
+}
+
+static tla_status launch_one(tla_ctx* h, KFn fn, size_t lds, int grid, int waves, const KArgs& a) {
+  TLA_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * waves), lds, h->stream, a);
+  TLA_HIP(hipGetLastError());
+  return TLA_OK;
 }
 
 tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& a0) {
   KArgs a = a0;
-  const int tb = p.tile, te = te_index(p.tile, p.engine), nwi = nw_index(p.waves);
-  a.ntmax = (a.n_max + tb - 1) / tb;
+  a.ntmax = (a.n_max + p.tile - 1) / p.tile;
   if (a.ntmax < 1) a.ntmax = 1;
   a.tau = h->tau;
   a.max_iter = h->max_iter;
-  bool lu = true;
-  size_t lds = lds_bytes(op, prec, tb, p.waves, a.ntmax, true);
-  if (op != TLA_POTRF && lds > (size_t)h->lds_limit) {
-    lu = false;
-    lds = lds_bytes(op, prec, tb, p.waves, a.ntmax, false);
-  }
-  if (lds > (size_t)h->lds_limit) return TLA_E_UNSUPPORTED;
-  KFn fn = nullptr;
-  if (prec == TLA_F64) {
-    if (op == TLA_POTRF) fn = potrf_f64_kernel(p.variant, te, nwi);
-    else if (op == TLA_TRSYL) fn = trsyl_f64_kernel(p.variant, te, nwi, lu);
-    else fn = trlyap_f64_kernel(p.variant, te, nwi, lu);
-  } else {
-    if (op == TLA_POTRF) fn = potrf_mixed_kernel(prec, p.variant, te, nwi);
-    else if (op == TLA_TRSYL) fn = trsyl_mixed_kernel(prec, p.variant, te, nwi, lu);
-    else fn = trlyap_mixed_kernel(prec, p.variant, te, nwi, lu);
-  }
+  a.only_flagged = 0;
+  size_t lds = 0;
+  const int pl = choose_placement(h, op, prec, p, a.ntmax, &lds);
+  if (pl < 0) return TLA_E_UNSUPPORTED;
+  const bool xg = prec != TLA_F64 && pl == 2;
+  KFn fn = kernel_for(op, prec, p, pl);
   if (!fn) return TLA_E_UNSUPPORTED;
+  if (xg) {
+    const size_t np = (size_t)a.ntmax * p.tile;
+    a.work_stride = (long long)(np * (np + 1));
+    tla_status s = ensure_buffers(h, (size_t)a.batch * a.work_stride * sizeof(double), a.batch);
+    if (s != TLA_OK) return s;
+    a.work = h->work;
+    if (!a.stat) a.stat = h->stat_buf;
+  }
   if (getenv("TLA_LOG"))
-    fprintf(stderr, "tla: op %d prec %d batch %d n_max %d plan(v%d t%d e%d w%d) lds %zu lu_lds %d\n", op, prec,
-            a.batch, a.n_max, p.variant, p.tile, p.engine, p.waves, lds, (int)lu);
-  TLA_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds));
-  hipLaunchKernelGGL(fn, dim3(a.batch), dim3(64 * p.waves), lds, h->stream, a);
-  TLA_HIP(hipGetLastError());
-  return TLA_OK;
+    fprintf(stderr, "tla: op %d prec %d batch %d n_max %d plan(v%d t%d e%d w%d) lds %zu placement %d\n", op, prec,
+            a.batch, a.n_max, p.variant, p.tile, p.engine, p.waves, lds, pl);
+  tla_status s = launch_one(h, fn, lds, a.batch, p.waves, a);
+  if (s != TLA_OK || !xg) return s;
+  // second pass: FP64 solve of the instances the mixed kernel left unconverged
+  size_t lds64 = 0;
+  const int pl64 = choose_placement(h, op, TLA_F64, p, a.ntmax, &lds64);
+  if (pl64 < 0) return TLA_E_UNSUPPORTED;
+  KFn fb = kernel_for(op, TLA_F64, p, pl64);
+  if (!fb) return TLA_E_UNSUPPORTED;
+  a.only_flagged = 1;
+  return launch_one(h, fb, lds64, a.batch, p.waves, a);
 }
 
 tla_plan pick_plan(tla_ctx* h, int op, int n, int prec, int batch) {

@@ -35,6 +35,10 @@ struct tla_ctx {
   std::vector<tla::TuneRecord> records;           // every measurement
   std::map<long long, tla_plan> best;             // key (op, n, prec) -> fastest plan
   tla::MlpState* mlp = nullptr;
+  double* work = nullptr;                         // FP64 workspace of the mixed kernels
+  size_t work_bytes = 0;
+  tla_stat* stat_buf = nullptr;                   // refinement records when the caller passes none
+  size_t stat_cap = 0;
   void release();
 };
 
@@ -44,6 +48,8 @@ bool table_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* p);
 bool mlp_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* p);
 void mlp_release(tla_ctx* h);
 tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& a);
+size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int placement);
+int choose_placement(tla_ctx* h, int op, int prec, const tla_plan& p, int ntmax, size_t* lds);
 bool plan_valid(int op, const tla_plan& p);
 int num_candidates(int op);
 bool candidate(int op, int i, tla_plan* p);

@@ -22,8 +22,9 @@ struct KArgs {
   const int* ldc;
   int* info;
   tla_stat* stat;
-  double* work;          // per-instance FP64 workspace (mixed path), may be null
-  long long work_stride; // doubles per instance in `work`
+  double* work;          // FP64 workspace, one slot per workgroup (mixed path), may be null
+  long long work_stride; // doubles per slot in `work`
+  int only_flagged;      // FP64 kernels: solve only instances whose stat asks for the FP64 path
 };
 
 }  // namespace tla

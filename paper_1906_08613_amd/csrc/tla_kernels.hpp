@@ -117,24 +117,61 @@ TLA_DI void scan_zero_denoms(const VA& A, const VB& B, int n, bool lower_only, i
   }
 }
 
-TLA_DI bool validate(const KArgs& g, int b, int& n) {
-  n = g.n[b];
+// One instance's operands and result slots (see KArgs for the roles).
+struct Inst {
+  int n;
+  const double* a;
+  int lda;
+  const double* b;
+  int ldb;
+  double* c;
+  int ldc;
+  int* info;
+  tla_stat* stat;
+};
+
+TLA_DI Inst fetch_uniform(const KArgs& g, int b) {
+  Inst in;
+  in.n = g.n[b];
+  in.a = g.a ? g.a[b] : nullptr;
+  in.lda = g.lda ? g.lda[b] : 1;
+  in.b = g.b ? g.b[b] : nullptr;
+  in.ldb = g.ldb ? g.ldb[b] : 1;
+  in.c = g.c[b];
+  in.ldc = g.ldc[b];
+  in.info = g.info + b;
+  in.stat = g.stat ? g.stat + b : nullptr;
+  return in;
+}
+
+// Checks n and the leading dimensions of the matrices the instance uses;
+// writes info = -1 / -2 (or 0 for n = 0) and returns false to skip it.
+TLA_DI bool validate(const Inst& in, int n_max, int& n) {
+  n = in.n;
   int bad = 0;
-  if (n < 0 || n > g.n_max) bad = -1;
+  if (n < 0 || n > n_max) bad = -1;
   else {
     const int m = n > 1 ? n : 1;
-    if (g.ldc[b] < m) bad = -2;
-    if (g.lda && g.lda[b] < m) bad = -2;
-    if (g.ldb && g.ldb[b] < m) bad = -2;
+    if (in.ldc < m) bad = -2;
+    if (in.a && in.lda < m) bad = -2;
+    if (in.b && in.ldb < m) bad = -2;
   }
   if (bad != 0 || n == 0) {
     if (threadIdx.x == 0) {
-      g.info[b] = bad;
-      if (g.stat) { g.stat[b].iters = 0; g.stat[b].flags = 0; g.stat[b].eta = 0.0; }
+      *in.info = bad;
+      if (in.stat) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
     }
     return false;
   }
   return true;
+}
+
+// Second (FP64) pass after a mixed launch whose FP64 solution did not fit in
+// LDS: only instances that the mixed kernel left unconverged are solved.
+TLA_DI bool skip_unflagged(const KArgs& g, const Inst& in) {
+  if (!g.only_flagged) return false;
+  if (in.n <= 0 || in.n > g.n_max || *in.info != 0) return true;
+  return (in.stat->flags & TLA_STAT_CONVERGED) != 0;
 }
 
 // LDS bytes of the FP64 kernels for tile count ntmax per dimension.
@@ -148,34 +185,38 @@ __host__ __device__ inline size_t lds_scratch_bytes(int nw, int tb, int elem) {
 
 // ================================================================ FP64
 template <int TB, int ENG, int NW, int VAR>
-__global__ __launch_bounds__(NW * 64) void k_potrf_f64(KArgs g) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int b = blockIdx.x;
+TLA_DI void potrf_f64_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
-  if (!validate(g, b, n)) return;
+  if (skip_unflagged(g, in)) return;
+  if (!validate(in, g.n_max, n)) return;
   const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
   double* A = reinterpret_cast<double*>(smem);
   double* wb = A + (size_t)g.ntmax * TB * (g.ntmax * TB + 1);
   int* s_info = reinterpret_cast<int*>(wb + NW * 4 * TB);
   if (threadIdx.x == 0) *s_info = 0;
-  ingest<double, NW>(A, ld, np, g.c[b], g.ldc[b], n, +1, 1.0);
+  ingest<double, NW>(A, ld, np, in.c, in.ldc, n, +1, 1.0);
   __syncthreads();
   Ctx<double> cx{n, nt, wb + wave_id() * 4 * TB, s_info};
   potrf_blocked<double, TB, ENG, NW, VAR>(colmajor(A, ld), cx);
   __syncthreads();
-  egress<double, NW>(g.c[b], g.ldc[b], n, A, ld, 1);
+  egress<double, NW>(in.c, in.ldc, n, A, ld, 1);
   if (threadIdx.x == 0) {
-    g.info[b] = *s_info;
-    if (g.stat) { g.stat[b].iters = 0; g.stat[b].flags = 0; g.stat[b].eta = 0.0; }
+    *in.info = *s_info;
+    if (in.stat && !g.only_flagged) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
   }
 }
 
-template <int TB, int ENG, int NW, int VAR, bool LU_LDS>
-__global__ __launch_bounds__(NW * 64) void k_trsyl_f64(KArgs g) {
+template <int TB, int ENG, int NW, int VAR>
+__global__ __launch_bounds__(NW * 64) void k_potrf_f64(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int b = blockIdx.x;
+  potrf_f64_body<TB, ENG, NW, VAR>(g, fetch_uniform(g, blockIdx.x), smem);
+}
+
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS>
+TLA_DI void trsyl_f64_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
-  if (!validate(g, b, n)) return;
+  if (skip_unflagged(g, in)) return;
+  if (!validate(in, g.n_max, n)) return;
   const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
   const size_t mat = (size_t)g.ntmax * TB * (g.ntmax * TB + 1);
   double* X = reinterpret_cast<double*>(smem);
@@ -184,10 +225,10 @@ __global__ __launch_bounds__(NW * 64) void k_trsyl_f64(KArgs g) {
   double* wb = LU_LDS ? Us + mat : Ls;
   int* s_info = reinterpret_cast<int*>(wb + NW * 4 * TB);
   if (threadIdx.x == 0) *s_info = INT_MAX;
-  ingest<double, NW>(X, ld, np, g.c[b], g.ldc[b], n, 0, 0.0);
+  ingest<double, NW>(X, ld, np, in.c, in.ldc, n, 0, 0.0);
   if constexpr (LU_LDS) {
-    ingest<double, NW>(Ls, ld, np, g.a[b], g.lda[b], n, -1, 0.0);
-    ingest<double, NW>(Us, ld, np, g.b[b], g.ldb[b], n, +1, 0.0);
+    ingest<double, NW>(Ls, ld, np, in.a, in.lda, n, -1, 0.0);
+    ingest<double, NW>(Us, ld, np, in.b, in.ldb, n, +1, 0.0);
   }
   __syncthreads();
   Ctx<double> cx{n, nt, wb + wave_id() * 4 * TB, s_info};
@@ -195,25 +236,30 @@ __global__ __launch_bounds__(NW * 64) void k_trsyl_f64(KArgs g) {
     scan_zero_denoms(colmajor(Ls, ld), colmajor(Us, ld), n, false, s_info);
     trsyl_blocked<double, TB, ENG, NW, VAR>(colmajor(X, ld), colmajor(Ls, ld), colmajor(Us, ld), cx);
   } else {
-    const GView<double> L = gview<double>(g.a[b], g.lda[b], n, -1);
-    const GView<double> U = gview<double>(g.b[b], g.ldb[b], n, +1);
+    const GView<double> L = gview<double>(in.a, in.lda, n, -1);
+    const GView<double> U = gview<double>(in.b, in.ldb, n, +1);
     scan_zero_denoms(L, U, n, false, s_info);
     trsyl_blocked<double, TB, ENG, NW, VAR>(colmajor(X, ld), L, U, cx);
   }
   __syncthreads();
-  egress<double, NW>(g.c[b], g.ldc[b], n, X, ld, 0);
+  egress<double, NW>(in.c, in.ldc, n, X, ld, 0);
   if (threadIdx.x == 0) {
-    g.info[b] = *s_info == INT_MAX ? 0 : *s_info;
-    if (g.stat) { g.stat[b].iters = 0; g.stat[b].flags = 0; g.stat[b].eta = 0.0; }
+    *in.info = *s_info == INT_MAX ? 0 : *s_info;
+    if (in.stat && !g.only_flagged) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
   }
 }
 
 template <int TB, int ENG, int NW, int VAR, bool LU_LDS>
-__global__ __launch_bounds__(NW * 64) void k_trlyap_f64(KArgs g) {
+__global__ __launch_bounds__(NW * 64) void k_trsyl_f64(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int b = blockIdx.x;
+  trsyl_f64_body<TB, ENG, NW, VAR, LU_LDS>(g, fetch_uniform(g, blockIdx.x), smem);
+}
+
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS>
+TLA_DI void trlyap_f64_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
-  if (!validate(g, b, n)) return;
+  if (skip_unflagged(g, in)) return;
+  if (!validate(in, g.n_max, n)) return;
   const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
   const size_t mat = (size_t)g.ntmax * TB * (g.ntmax * TB + 1);
   double* X = reinterpret_cast<double*>(smem);
@@ -221,8 +267,8 @@ __global__ __launch_bounds__(NW * 64) void k_trlyap_f64(KArgs g) {
   double* wb = LU_LDS ? Ls + mat : Ls;
   int* s_info = reinterpret_cast<int*>(wb + NW * 4 * TB);
   if (threadIdx.x == 0) *s_info = INT_MAX;
-  ingest<double, NW>(X, ld, np, g.c[b], g.ldc[b], n, -1, 0.0);
-  if constexpr (LU_LDS) ingest<double, NW>(Ls, ld, np, g.a[b], g.lda[b], n, -1, 0.0);
+  ingest<double, NW>(X, ld, np, in.c, in.ldc, n, -1, 0.0);
+  if constexpr (LU_LDS) ingest<double, NW>(Ls, ld, np, in.a, in.lda, n, -1, 0.0);
   __syncthreads();
   mirror_lower(X, ld, np);
   __syncthreads();
@@ -231,16 +277,22 @@ __global__ __launch_bounds__(NW * 64) void k_trlyap_f64(KArgs g) {
     scan_zero_denoms(colmajor(Ls, ld), colmajor(Ls, ld), n, true, s_info);
     trlyap_blocked<double, TB, ENG, NW, VAR>(colmajor(X, ld), colmajor(Ls, ld), cx);
   } else {
-    const GView<double> L = gview<double>(g.a[b], g.lda[b], n, -1);
+    const GView<double> L = gview<double>(in.a, in.lda, n, -1);
     scan_zero_denoms(L, L, n, true, s_info);
     trlyap_blocked<double, TB, ENG, NW, VAR>(colmajor(X, ld), L, cx);
   }
   __syncthreads();
-  egress<double, NW>(g.c[b], g.ldc[b], n, X, ld, 2);
+  egress<double, NW>(in.c, in.ldc, n, X, ld, 2);
   if (threadIdx.x == 0) {
-    g.info[b] = *s_info == INT_MAX ? 0 : *s_info;
-    if (g.stat) { g.stat[b].iters = 0; g.stat[b].flags = 0; g.stat[b].eta = 0.0; }
+    *in.info = *s_info == INT_MAX ? 0 : *s_info;
+    if (in.stat && !g.only_flagged) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
   }
+}
+
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS>
+__global__ __launch_bounds__(NW * 64) void k_trlyap_f64(KArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  trlyap_f64_body<TB, ENG, NW, VAR, LU_LDS>(g, fetch_uniform(g, blockIdx.x), smem);
 }
 
 }  // namespace tla

@@ -63,11 +63,11 @@ TLA_DI bool refine_decide(RefineState& st, double eta, double tau, int max_iter)
   return false;
 }
 
-TLA_DI void write_stat(const KArgs& g, int b, const RefineState& st) {
-  if (threadIdx.x == 0 && g.stat) {
-    g.stat[b].iters = st.it;
-    g.stat[b].flags = st.flags;
-    g.stat[b].eta = st.eta;
+TLA_DI void write_stat(const Inst& in, const RefineState& st) {
+  if (threadIdx.x == 0 && in.stat) {
+    in.stat->iters = st.it;
+    in.stat->flags = st.flags;
+    in.stat->eta = st.eta;
   }
 }
 
@@ -84,12 +84,20 @@ struct MixedLds {
   int* info;
 };
 
-template <int TB, int NW>
-TLA_DI MixedLds carve(unsigned char* smem, int ntmax, int naux) {
-  const size_t np = (size_t)ntmax * TB, mat = np * (np + 1);
+// With XG the FP64 solution lives in a global workspace slot instead (sizes
+// where it does not fit next to W); every access to it is then separated by
+// workgroup barriers, and the FP64 fallback runs as a second launch.
+template <int TB, int NW, bool XG>
+TLA_DI MixedLds carve(unsigned char* smem, const KArgs& g, int naux) {
+  const size_t np = (size_t)g.ntmax * TB, mat = np * (np + 1);
   MixedLds m;
-  m.Xd = reinterpret_cast<double*>(smem);
-  m.W = reinterpret_cast<float*>(m.Xd + mat);
+  if constexpr (XG) {
+    m.Xd = g.work + (size_t)blockIdx.x * g.work_stride;
+    m.W = reinterpret_cast<float*>(smem);
+  } else {
+    m.Xd = reinterpret_cast<double*>(smem);
+    m.W = reinterpret_cast<float*>(m.Xd + mat);
+  }
   m.A1 = m.W + mat;
   m.A2 = m.A1 + (naux >= 1 ? mat : 0);
   float* after = m.A2 + (naux >= 2 ? mat : 0);
@@ -114,18 +122,16 @@ TLA_DI bool all_finite_lds(const T* W, int ldw, int n) {
 }
 
 // ===================================================== Sylvester, mixed
-template <int TB, int ENG, int NW, int VAR, bool LU_LDS>
-__global__ __launch_bounds__(NW * 64) void k_trsyl_mixed(KArgs g) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int b = blockIdx.x;
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG>
+TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
-  if (!validate(g, b, n)) return;
+  if (!validate(in, g.n_max, n)) return;
   const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
-  const MixedLds m = carve<TB, NW>(smem, g.ntmax, LU_LDS ? 2 : 0);
-  const double* Lg = g.a[b];
-  const double* Ug = g.b[b];
-  double* Cg = g.c[b];
-  const int ldl = g.lda[b], ldu = g.ldb[b], ldc = g.ldc[b];
+  const MixedLds m = carve<TB, NW, XG>(smem, g, LU_LDS ? 2 : 0);
+  const double* Lg = in.a;
+  const double* Ug = in.b;
+  double* Cg = in.c;
+  const int ldl = in.lda, ldu = in.ldb, ldc = in.ldc;
   const GView<double> L64 = gview<double>(Lg, ldl, n, -1);
   const GView<double> U64 = gview<double>(Ug, ldu, n, +1);
   const GView<double> C64 = gview<double>(Cg, ldc, n, 0);
@@ -205,7 +211,8 @@ __global__ __launch_bounds__(NW * 64) void k_trsyl_mixed(KArgs g) {
     }
   }
   __syncthreads();
-  if (info0 == 0 && !(st.flags & TLA_STAT_CONVERGED)) {
+  const bool fb = info0 == 0 && !(st.flags & TLA_STAT_CONVERGED);
+  if (!XG && fb) {
     // FP64 solve of the instance (fallback or breakdown)
     ingest<double, NW>(m.Xd, ld, np, Cg, ldc, n, 0, 0.0);
     __syncthreads();
@@ -215,23 +222,27 @@ __global__ __launch_bounds__(NW * 64) void k_trsyl_mixed(KArgs g) {
     trsyl_blocked<double, TB, ENG64, NW, VAR>(colmajor(m.Xd, ld), L64, U64, cd);
     __syncthreads();
   }
-  if (info0 == 0) egress<double, NW>(Cg, ldc, n, m.Xd, ld, 0);
-  if (threadIdx.x == 0) g.info[b] = info0;
-  write_stat(g, b, st);
+  if (info0 == 0 && !(XG && fb)) egress<double, NW>(Cg, ldc, n, m.Xd, ld, 0);
+  if (threadIdx.x == 0) *in.info = info0;
+  write_stat(in, st);
+}
+
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG>
+__global__ __launch_bounds__(NW * 64) void k_trsyl_mixed(KArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  trsyl_mixed_body<TB, ENG, NW, VAR, LU_LDS, XG>(g, fetch_uniform(g, blockIdx.x), smem);
 }
 
 // ===================================================== Lyapunov, mixed
-template <int TB, int ENG, int NW, int VAR, bool LU_LDS>
-__global__ __launch_bounds__(NW * 64) void k_trlyap_mixed(KArgs g) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int b = blockIdx.x;
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG>
+TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
-  if (!validate(g, b, n)) return;
+  if (!validate(in, g.n_max, n)) return;
   const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
-  const MixedLds m = carve<TB, NW>(smem, g.ntmax, LU_LDS ? 1 : 0);
-  const double* Lg = g.a[b];
-  double* Sg = g.c[b];
-  const int ldl = g.lda[b], lds = g.ldc[b];
+  const MixedLds m = carve<TB, NW, XG>(smem, g, LU_LDS ? 1 : 0);
+  const double* Lg = in.a;
+  double* Sg = in.c;
+  const int ldl = in.lda, lds = in.ldc;
   const GView<double> L64 = gview<double>(Lg, ldl, n, -1);
   const GView<double> S64 = gview<double>(Sg, lds, n, -2);
   constexpr int E64 = F64Eng<TB>::value;
@@ -317,7 +328,8 @@ __global__ __launch_bounds__(NW * 64) void k_trlyap_mixed(KArgs g) {
     }
   }
   __syncthreads();
-  if (info0 == 0 && !(st.flags & TLA_STAT_CONVERGED)) {
+  const bool fb = info0 == 0 && !(st.flags & TLA_STAT_CONVERGED);
+  if (!XG && fb) {
     ingest<double, NW>(m.Xd, ld, np, Sg, lds, n, -1, 0.0);
     __syncthreads();
     mirror_lower(m.Xd, ld, np);
@@ -327,9 +339,15 @@ __global__ __launch_bounds__(NW * 64) void k_trlyap_mixed(KArgs g) {
     trlyap_blocked<double, TB, ENG64, NW, VAR>(colmajor(m.Xd, ld), L64, cd);
     __syncthreads();
   }
-  if (info0 == 0) egress<double, NW>(Sg, lds, n, m.Xd, ld, 2);
-  if (threadIdx.x == 0) g.info[b] = info0;
-  write_stat(g, b, st);
+  if (info0 == 0 && !(XG && fb)) egress<double, NW>(Sg, lds, n, m.Xd, ld, 2);
+  if (threadIdx.x == 0) *in.info = info0;
+  write_stat(in, st);
+}
+
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG>
+__global__ __launch_bounds__(NW * 64) void k_trlyap_mixed(KArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  trlyap_mixed_body<TB, ENG, NW, VAR, LU_LDS, XG>(g, fetch_uniform(g, blockIdx.x), smem);
 }
 
 // ====================================================== Cholesky, mixed
@@ -384,16 +402,14 @@ TLA_DI void newton_correction(const View<T>& Wv, const View<T>& Xv, const View<d
   }
 }
 
-template <int TB, int ENG, int NW, int VAR>
-__global__ __launch_bounds__(NW * 64) void k_potrf_mixed(KArgs g) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int b = blockIdx.x;
+template <int TB, int ENG, int NW, int VAR, bool XG>
+TLA_DI void potrf_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
-  if (!validate(g, b, n)) return;
+  if (!validate(in, g.n_max, n)) return;
   const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
-  const MixedLds m = carve<TB, NW>(smem, g.ntmax, 1);
-  double* Ag = g.c[b];
-  const int lda = g.ldc[b];
+  const MixedLds m = carve<TB, NW, XG>(smem, g, 1);
+  double* Ag = in.c;
+  const int lda = in.ldc;
   const GView<double> A64 = gview<double>(Ag, lda, n, 2);
   constexpr int E64 = F64Eng<TB>::value;
   if (threadIdx.x == 0) *m.info = 0;
@@ -450,7 +466,8 @@ __global__ __launch_bounds__(NW * 64) void k_potrf_mixed(KArgs g) {
   }
   __syncthreads();
   int info0 = 0;
-  if (!(st.flags & TLA_STAT_CONVERGED)) {
+  const bool fb = !(st.flags & TLA_STAT_CONVERGED);
+  if (!XG && fb) {
     if (threadIdx.x == 0) *m.info = 0;
     ingest<double, NW>(m.Xd, ld, np, Ag, lda, n, +1, 1.0);
     __syncthreads();
@@ -460,9 +477,15 @@ __global__ __launch_bounds__(NW * 64) void k_potrf_mixed(KArgs g) {
     __syncthreads();
     info0 = *m.info;
   }
-  egress<double, NW>(Ag, lda, n, m.Xd, ld, 1);
-  if (threadIdx.x == 0) g.info[b] = info0;
-  write_stat(g, b, st);
+  if (!(XG && fb)) egress<double, NW>(Ag, lda, n, m.Xd, ld, 1);
+  if (threadIdx.x == 0) *in.info = info0;
+  write_stat(in, st);
+}
+
+template <int TB, int ENG, int NW, int VAR, bool XG>
+__global__ __launch_bounds__(NW * 64) void k_potrf_mixed(KArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  potrf_mixed_body<TB, ENG, NW, VAR, XG>(g, fetch_uniform(g, blockIdx.x), smem);
 }
 
 }  // namespace tla

@@ -15,15 +15,15 @@ KFn trlyap_mixed_kernel_bf16(int, int, int, int);
 // FP32 vector-ALU engines (te 0, 1) do not depend on the 16-bit type
 static int eff_prec(int prec, int te) { return te < 2 ? TLA_MIXED_F32 : prec; }
 
-KFn potrf_mixed_kernel(int prec, int var, int te, int nwi) {
+KFn potrf_mixed_kernel(int prec, int var, int te, int nwi, int pl) {
   switch (eff_prec(prec, te)) {
-    case TLA_MIXED_F32: return potrf_mixed_kernel_f32(var, te, nwi, 0);
-    case TLA_MIXED_F16: return potrf_mixed_kernel_f16(var, te, nwi, 0);
-    case TLA_MIXED_BF16: return potrf_mixed_kernel_bf16(var, te, nwi, 0);
+    case TLA_MIXED_F32: return potrf_mixed_kernel_f32(var, te, nwi, pl);
+    case TLA_MIXED_F16: return potrf_mixed_kernel_f16(var, te, nwi, pl);
+    case TLA_MIXED_BF16: return potrf_mixed_kernel_bf16(var, te, nwi, pl);
   }
   return nullptr;
 }
-KFn trsyl_mixed_kernel(int prec, int var, int te, int nwi, bool lu) {
+KFn trsyl_mixed_kernel(int prec, int var, int te, int nwi, int lu) {
   switch (eff_prec(prec, te)) {
     case TLA_MIXED_F32: return trsyl_mixed_kernel_f32(var, te, nwi, lu);
     case TLA_MIXED_F16: return trsyl_mixed_kernel_f16(var, te, nwi, lu);
@@ -31,7 +31,7 @@ KFn trsyl_mixed_kernel(int prec, int var, int te, int nwi, bool lu) {
   }
   return nullptr;
 }
-KFn trlyap_mixed_kernel(int prec, int var, int te, int nwi, bool lu) {
+KFn trlyap_mixed_kernel(int prec, int var, int te, int nwi, int lu) {
   switch (eff_prec(prec, te)) {
     case TLA_MIXED_F32: return trlyap_mixed_kernel_f32(var, te, nwi, lu);
     case TLA_MIXED_F16: return trlyap_mixed_kernel_f16(var, te, nwi, lu);

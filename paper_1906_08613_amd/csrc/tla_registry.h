@@ -20,7 +20,10 @@ namespace tla {
 // Mixed-precision kernels.  te 0/1 run FP32 vector-ALU tile updates; te 2
 // runs them on the matrix cores in the input type named by prec
 // (TLA_MIXED_F32: FP32, TLA_MIXED_F16: FP16, TLA_MIXED_BF16: BF16).
-KFn potrf_mixed_kernel(int prec, int var, int te, int nwi);
-KFn trsyl_mixed_kernel(int prec, int var, int te, int nwi, bool lu_lds);
-KFn trlyap_mixed_kernel(int prec, int var, int te, int nwi, bool lu_lds);
+// placement: potrf 0 = FP64 solution in LDS, 1 = in the global workspace;
+// trsyl/trlyap 0 = coefficients and solution in LDS, 1 = coefficients read
+// through the caches, 2 = solution in the global workspace as well.
+KFn potrf_mixed_kernel(int prec, int var, int te, int nwi, int placement);
+KFn trsyl_mixed_kernel(int prec, int var, int te, int nwi, int placement);
+KFn trlyap_mixed_kernel(int prec, int var, int te, int nwi, int placement);
 }  // namespace tla

@@ -1,29 +1,30 @@
 // Mixed-precision trlyap kernels with bf16 tile updates on the matrix cores.
+// Index: (variant, tile/engine, waves, placement); placement 0: coefficients and FP64 solution in LDS; 1: coefficients read through the caches; 2: FP64 solution in the global workspace too.
 #include "tla_mixed.hpp"
 #include "tla_registry.h"
 
 namespace tla {
 namespace {
-constexpr int kLU = 1 ? 2 : 1;
-template <int VAR, int TE, int NWI, int LU>
+constexpr int kPL = 3;
+template <int VAR, int TE, int NWI, int PL>
 void fill(KFn* tab) {
   constexpr int TB = TE == 0 ? 8 : 16;
   constexpr int ENG = TE == 2 ? ENG_MFMA_BF16 : ENG_VALU;
   constexpr int NW = NWI == 0 ? 1 : (NWI == 1 ? 2 : 4);
-  if constexpr (1) tab[((VAR * kNumTE + TE) * kNumNW + NWI) * kLU + LU] = reinterpret_cast<KFn>(&k_trlyap_mixed<TB, ENG, NW, VAR, LU == 1>);
-  else tab[((VAR * kNumTE + TE) * kNumNW + NWI) * kLU + LU] = reinterpret_cast<KFn>(&k_trlyap_mixed<TB, ENG, NW, VAR>);
-  if constexpr (LU + 1 < kLU) fill<VAR, TE, NWI, LU + 1>(tab);
+  tab[((VAR * kNumTE + TE) * kNumNW + NWI) * kPL + PL] = reinterpret_cast<KFn>(&k_trlyap_mixed<TB, ENG, NW, VAR, PL == 0, PL == 2>);
+  if constexpr (PL + 1 < kPL) fill<VAR, TE, NWI, PL + 1>(tab);
   else if constexpr (NWI + 1 < kNumNW) fill<VAR, TE, NWI + 1, 0>(tab);
   else if constexpr (TE + 1 < kNumTE) fill<VAR, TE + 1, 0, 0>(tab);
   else if constexpr (VAR + 1 < LYA_NVAR) fill<VAR + 1, 2, 0, 0>(tab);
 }
 }  // namespace
 
-KFn trlyap_mixed_kernel_bf16(int var, int te, int nwi, int lu) {
-  static KFn tab[LYA_NVAR * kNumTE * kNumNW * kLU] = {};
+KFn trlyap_mixed_kernel_bf16(int var, int te, int nwi, int pl) {
+  static KFn tab[LYA_NVAR * kNumTE * kNumNW * kPL] = {};
   static bool init = false;
   if (!init) { fill<0, 2, 0, 0>(tab); init = true; }
-  if (var < 0 || var >= LYA_NVAR || te < 2 || te >= kNumTE || nwi < 0 || nwi >= kNumNW) return nullptr;
-  return tab[((var * kNumTE + te) * kNumNW + nwi) * kLU + (kLU == 2 ? lu : 0)];
+  if (var < 0 || var >= LYA_NVAR || te < 2 || te >= kNumTE || nwi < 0 || nwi >= kNumNW || pl < 0 || pl >= kPL)
+    return nullptr;
+  return tab[((var * kNumTE + te) * kNumNW + nwi) * kPL + pl];
 }
 }  // namespace tla

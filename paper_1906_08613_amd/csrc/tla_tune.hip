@@ -237,4 +237,10 @@ extern "C" tla_status tla_load_table(tla_handle h, const char* path) {
   return TLA_OK;
 }
 
-void tla_ctx::release() { tla::mlp_release(this); }
+void tla_ctx::release() {
+  tla::mlp_release(this);
+  if (work) hipFree(work);
+  if (stat_buf) hipFree(stat_buf);
+  work = nullptr;
+  stat_buf = nullptr;
+}

@@ -199,3 +199,35 @@ def test_every_mixed_plan(h, orc, op):
             X, ops = solve(h, op, mats, prec, plan)
             assert eta_fn(*mats, X).max() <= 1e-12, (prec, plan)
             assert rel_err(X, Xr).max() <= fwd_tol(n, 1e3), (prec, plan)
+
+
+@pytest.mark.parametrize("op", ["potrf", "trsyl", "trlyap"])
+@pytest.mark.parametrize("n", [100, 128])
+def test_mixed_large_n_placements(h, orc, op, n):
+    # the FP64 solution no longer fits next to the FP32 work matrix: it lives
+    # in the handle's workspace and the FP64 fallback is a second launch
+    kappa = 1e4
+    mats = problem(op, n, 6, kappa, tag="large")
+    Xr, ir, eta_fn = oracle_solve(orc, op, mats)
+    for prec in ["mixed_f32", "mixed_bf16"]:
+        print(f"{op} n={n} {prec}", flush=True)
+        X, ops = solve(h, op, mats, prec)
+        assert np.all(ops.info.cpu().numpy() == ir)
+        assert eta_fn(*mats, X).max() <= 1e-12, prec
+        assert rel_err(X, Xr).max() <= fwd_tol(n, kappa), prec
+
+
+@pytest.mark.parametrize("op", ["potrf", "trsyl", "trlyap"])
+def test_second_pass_fallback_matches_fp64(h, orc, op):
+    n = 128
+    mats = problem(op, n, 4, 1e2, tag="fb128")
+    plan = (0, 16, 1, 4)
+    h.set_refine(1e-13, 0)
+    try:
+        X, ops = solve(h, op, mats, "mixed_f32", plan)
+    finally:
+        h.set_refine(1e-13, 8)
+    st = tla.stat_view(ops.stat)
+    assert np.all(st["flags"] & tla.STAT_FALLBACK)
+    Y, _ = solve(h, op, mats, "f64", plan)
+    assert np.array_equal(X, Y)
