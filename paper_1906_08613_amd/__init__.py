@@ -291,3 +291,70 @@ def trlyap(h: Handle, L, S, prec="f64", ops: Operands | None = None):
     h.trlyap_batched(prec, ops.batch, ops.n_max, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1],
                      ops.info, ops.stat)
     return ops
+
+
+class RaggedBatch:
+    """Device storage and tla_desc array for a ragged batch.
+
+    ops: sequence of POTRF/TRSYL/TRLYAP; mats[b]: tuple of numpy matrices of
+    instance b in the roles of tla_desc (potrf: (A,), trsyl: (L, U, C),
+    trlyap: (L, S)), indexed [i, j].  All matrices of all instances share one
+    flat float64 device buffer, each stored column-major with ld = n + pad.
+    """
+
+    def __init__(self, ops, mats, device="cuda", pad=0):
+        import torch
+        self.ops = [int(o) for o in ops]
+        self.batch = len(self.ops)
+        sizes, offs = [], []
+        total = 0
+        for b, m in enumerate(mats):
+            n = m[0].shape[-1]
+            ld = n + pad
+            o = []
+            for _ in m:
+                o.append(total)
+                total += max(ld * n, 1)
+            offs.append(o)
+            sizes.append((n, ld))
+        host = np.zeros(max(total, 1), dtype=np.float64)
+        for b, m in enumerate(mats):
+            n, ld = sizes[b]
+            for k, M in enumerate(m):
+                blk = np.zeros((n, ld))
+                blk[:, :n] = np.asarray(M, dtype=np.float64).T
+                host[offs[b][k]:offs[b][k] + ld * n] = blk.reshape(-1)
+        self.buf = torch.from_numpy(host).to(device)
+        base = self.buf.data_ptr()
+        d = np.zeros(self.batch, dtype=DESC_NP)
+        for b in range(self.batch):
+            n, ld = sizes[b]
+            d["op"][b] = self.ops[b]
+            d["n"][b] = n
+            d["lda"][b] = d["ldb"][b] = d["ldc"][b] = ld
+            ptr = [base + 8 * o for o in offs[b]]
+            if self.ops[b] == POTRF:
+                d["a"][b] = ptr[0]
+            elif self.ops[b] == TRSYL:
+                d["a"][b], d["b"][b], d["c"][b] = ptr
+            else:
+                d["a"][b], d["c"][b] = ptr
+        self.sizes, self.offs = sizes, offs
+        self.desc_host = d
+        self.desc = torch.from_numpy(d.view(np.uint8).copy()).to(device)
+        self.info = torch.zeros(self.batch, dtype=torch.int32, device=device)
+        self.stat = torch.zeros((self.batch, 2), dtype=torch.float64, device=device)
+        self.n_max = max([s[0] for s in sizes] + [0])
+
+    def result(self, b):
+        """Output matrix of instance b (numpy, [i, j]): A/X for potrf, X otherwise."""
+        n, ld = self.sizes[b]
+        k = 0 if self.ops[b] == POTRF else len(self.offs[b]) - 1
+        o = self.offs[b][k]
+        blk = self.buf[o:o + ld * n].view(n, ld).cpu().numpy()
+        return np.ascontiguousarray(blk[:, :n].T)
+
+
+def ragged(h: Handle, rb: RaggedBatch, prec="f64", n_max=None):
+    h.ragged_batched(prec, rb.batch, rb.n_max if n_max is None else n_max, rb.desc, rb.info, rb.stat)
+    return rb

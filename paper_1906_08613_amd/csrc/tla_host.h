@@ -20,6 +20,7 @@ struct TuneRecord {
 };
 
 struct MlpState;  // learned cost model (tla_mlp.hip)
+struct RagState;  // ragged batches: work-list buffers and captured graphs (tla_ragged.hip)
 
 }  // namespace tla
 
@@ -35,6 +36,7 @@ struct tla_ctx {
   std::vector<tla::TuneRecord> records;           // every measurement
   std::map<long long, tla_plan> best;             // key (op, n, prec) -> fastest plan
   tla::MlpState* mlp = nullptr;
+  tla::RagState* rag = nullptr;
   double* work = nullptr;                         // FP64 workspace of the mixed kernels
   size_t work_bytes = 0;
   tla_stat* stat_buf = nullptr;                   // refinement records when the caller passes none
@@ -47,6 +49,7 @@ inline long long table_key(int op, int n, int prec) { return ((long long)op * 16
 bool table_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* p);
 bool mlp_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* p);
 void mlp_release(tla_ctx* h);
+void ragged_release(tla_ctx* h);
 tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& a);
 size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int placement);
 int choose_placement(tla_ctx* h, int op, int prec, const tla_plan& p, int ntmax, size_t* lds);

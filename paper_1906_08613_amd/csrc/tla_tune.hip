@@ -239,6 +239,7 @@ extern "C" tla_status tla_load_table(tla_handle h, const char* path) {
 
 void tla_ctx::release() {
   tla::mlp_release(this);
+  tla::ragged_release(this);
   if (work) hipFree(work);
   if (stat_buf) hipFree(stat_buf);
   work = nullptr;
