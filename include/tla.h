@@ -35,6 +35,7 @@
  *        <= 0 or NaN) in the precision that ran last; A is then unspecified.
  *        trsyl/trlyap: 1 + (i + j*n) of the first zero denominator
  *        l_ii + u_jj (resp. l_ii + l_jj) in column-major order; X unspecified.
+ *   -3   (ragged batches only) the descriptor names no known operation
  * n[b] = 0 is a quick return with info 0.  Nothing crosses the ABI as an
  * exception.
  */
@@ -157,6 +158,39 @@ tla_status tla_time_plan(tla_handle h, tla_op op, int n, tla_prec prec, int batc
 tla_status tla_save_table(tla_handle h, const char *path);
 tla_status tla_load_table(tla_handle h, const char *path);
 tla_status tla_set_picker(tla_handle h, tla_picker mode);
+
+/* ------------------------------------------------- learned cost model */
+/* A small MLP (features -> 64 ReLU -> 64 ReLU -> 1, FP32) predicts the log
+ * run time of a plan so that plans can be picked without timing every
+ * candidate -- the model-based replacement of autotuning that the paper lists
+ * as future work (Limitations and future work paragraph).  It is trained on
+ * the GPU, by the library's own forward/backward/Adam kernels, on the
+ * measurements in the handle's tuning table; the table remains the fallback.
+ * Parameters are one flat FP32 array (W1[64][F], b1[64], W2[64][64], b2[64],
+ * w3[64], b3), F = tla_mlp_num_features().  Host arrays; calls synchronise. */
+int tla_mlp_num_params(void);
+int tla_mlp_num_features(void);
+/* Feature vector of (op, n, prec, batch, plan) into out[F]. */
+tla_status tla_mlp_features(tla_op op, int n, tla_prec prec, int batch, const tla_plan *plan, float *out);
+tla_status tla_mlp_set_params(tla_handle h, const float *params);
+tla_status tla_mlp_get_params(tla_handle h, float *params);
+/* Mean squared error of the network on N samples X[N][F] with targets T[N],
+ * and its gradient (grad[num_params], may be NULL) and outputs (Y[N], may be
+ * NULL), computed by the device kernels. */
+tla_status tla_mlp_forward_backward(tla_handle h, int N, const float *X, const float *T, float *loss,
+                                    float *grad, float *Y);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the given gradient. */
+tla_status tla_mlp_adam_step(tla_handle h, const float *grad, float lr);
+/* Train from a seeded initialisation on the tuning table's measurements,
+ * leaving out n with n % exclude_mod == 0 when exclude_mod > 0 (held-out
+ * sizes); `epochs` full-batch Adam steps; final training loss out. */
+tla_status tla_mlp_train(tla_handle h, int epochs, float lr, unsigned long long seed, int exclude_mod,
+                         float *final_loss);
+/* Predicted seconds per launch of a plan. */
+tla_status tla_mlp_predict(tla_handle h, tla_op op, int n, tla_prec prec, int batch, const tla_plan *plan,
+                           double *seconds);
+tla_status tla_mlp_save(tla_handle h, const char *path);
+tla_status tla_mlp_load(tla_handle h, const char *path);
 
 /* ---------------------------------------------------------- refinement */
 /* Refinement tolerance on the backward error eta (default 1e-13) and the

@@ -35,6 +35,9 @@ SYMBOLS = [
     "tla_set_plan", "tla_get_plan", "tla_num_candidates", "tla_candidate", "tla_variant_name",
     "tla_tune", "tla_time_plan", "tla_save_table", "tla_load_table", "tla_set_picker",
     "tla_set_refine", "tla_status_string",
+    "tla_mlp_num_params", "tla_mlp_num_features", "tla_mlp_features", "tla_mlp_set_params",
+    "tla_mlp_get_params", "tla_mlp_forward_backward", "tla_mlp_adam_step", "tla_mlp_train",
+    "tla_mlp_predict", "tla_mlp_save", "tla_mlp_load",
 ]
 
 
@@ -98,6 +101,17 @@ def lib():
             "tla_set_picker": (I, [V, I]),
             "tla_set_refine": (I, [V, D, I]),
             "tla_status_string": (ctypes.c_char_p, [I]),
+            "tla_mlp_num_params": (I, []),
+            "tla_mlp_num_features": (I, []),
+            "tla_mlp_features": (I, [I, I, I, I, ctypes.POINTER(Plan), P]),
+            "tla_mlp_set_params": (I, [V, P]),
+            "tla_mlp_get_params": (I, [V, P]),
+            "tla_mlp_forward_backward": (I, [V, I, P, P, P, P, P]),
+            "tla_mlp_adam_step": (I, [V, P, ctypes.c_float]),
+            "tla_mlp_train": (I, [V, I, ctypes.c_float, ctypes.c_ulonglong, I, P]),
+            "tla_mlp_predict": (I, [V, I, I, I, I, ctypes.POINTER(Plan), ctypes.POINTER(D)]),
+            "tla_mlp_save": (I, [V, ctypes.c_char_p]),
+            "tla_mlp_load": (I, [V, ctypes.c_char_p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -205,6 +219,52 @@ class Handle:
                              b.ctypes.data_as(ctypes.c_void_p), len(c), c.ctypes.data_as(ctypes.c_void_p),
                              batch, reps), "tla_tune")
 
+    # ------------------------------------------------- learned cost model
+    def mlp_set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        check(lib().tla_mlp_set_params(self.h, p.ctypes.data_as(ctypes.c_void_p)), "tla_mlp_set_params")
+
+    def mlp_get_params(self):
+        p = np.zeros(mlp_num_params(), dtype=np.float32)
+        check(lib().tla_mlp_get_params(self.h, p.ctypes.data_as(ctypes.c_void_p)), "tla_mlp_get_params")
+        return p
+
+    def mlp_forward_backward(self, X, T):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        N = X.shape[0]
+        loss = np.zeros(1, dtype=np.float32)
+        grad = np.zeros(mlp_num_params(), dtype=np.float32)
+        Y = np.zeros(N, dtype=np.float32)
+        vp = ctypes.c_void_p
+        check(lib().tla_mlp_forward_backward(self.h, N, X.ctypes.data_as(vp), T.ctypes.data_as(vp),
+                                             loss.ctypes.data_as(vp), grad.ctypes.data_as(vp),
+                                             Y.ctypes.data_as(vp)), "tla_mlp_forward_backward")
+        return float(loss[0]), grad, Y
+
+    def mlp_adam_step(self, grad, lr):
+        g = np.ascontiguousarray(grad, dtype=np.float32)
+        check(lib().tla_mlp_adam_step(self.h, g.ctypes.data_as(ctypes.c_void_p), lr), "tla_mlp_adam_step")
+
+    def mlp_train(self, epochs=2000, lr=3e-3, seed=1, exclude_mod=0):
+        loss = np.zeros(1, dtype=np.float32)
+        check(lib().tla_mlp_train(self.h, epochs, lr, seed, exclude_mod, loss.ctypes.data_as(ctypes.c_void_p)),
+              "tla_mlp_train")
+        return float(loss[0])
+
+    def mlp_predict(self, op, n, prec, batch, plan):
+        p = Plan(*plan) if not isinstance(plan, Plan) else plan
+        s = ctypes.c_double()
+        check(lib().tla_mlp_predict(self.h, OPS.get(op, op), n, _prec(prec), batch, ctypes.byref(p),
+                                    ctypes.byref(s)), "tla_mlp_predict")
+        return s.value
+
+    def mlp_save(self, path):
+        check(lib().tla_mlp_save(self.h, path.encode()), "tla_mlp_save")
+
+    def mlp_load(self, path):
+        check(lib().tla_mlp_load(self.h, path.encode()), "tla_mlp_load")
+
     def save_table(self, path):
         check(lib().tla_save_table(self.h, path.encode()), "tla_save_table")
 
@@ -220,6 +280,22 @@ def candidate(op, i):
     p = Plan()
     check(lib().tla_candidate(OPS.get(op, op), i, ctypes.byref(p)), "tla_candidate")
     return p
+
+
+def mlp_num_params():
+    return lib().tla_mlp_num_params()
+
+
+def mlp_num_features():
+    return lib().tla_mlp_num_features()
+
+
+def mlp_features(op, n, prec, batch, plan):
+    p = Plan(*plan) if not isinstance(plan, Plan) else plan
+    f = np.zeros(mlp_num_features(), dtype=np.float32)
+    check(lib().tla_mlp_features(OPS.get(op, op), n, _prec(prec), batch, ctypes.byref(p),
+                                 f.ctypes.data_as(ctypes.c_void_p)), "tla_mlp_features")
+    return f
 
 
 def variant_name(op, v):

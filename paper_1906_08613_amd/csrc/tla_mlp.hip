@@ -1,6 +1,429 @@
-// Learned cost model (placeholder until the MLP kernels land).
+// Learned cost model: a small MLP that predicts the log run time of a plan
+// for (op, n, precision, batch), used to pick plans without timing every
+// candidate.  The paper names a model-based replacement of its autotuning
+// loops as future work (Limitations and future work paragraph); here the
+// network is trained on the autotuner's own measurements, on the GPU, by the
+// forward, backward and Adam kernels below, and the measured table stays the
+// fallback and the judge of its picks.
+//
+// Network: in (kMlpIn features) -> 64 ReLU -> 64 ReLU -> 1, FP32, loss
+// = mean squared error on standardised log seconds.  Parameters are one flat
+// FP32 array: W1[64][kMlpIn], b1[64], W2[64][64], b2[64], w3[64], b3.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
 #include "tla_host.h"
+
 namespace tla {
-bool mlp_pick(tla_ctx*, int, int, int, int, tla_plan*) { return false; }
-void mlp_release(tla_ctx*) {}
+
+constexpr int kMlpIn = 24, kMlpH = 64;
+constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kMlpH * kMlpIn, kOffW2 = kOffB1 + kMlpH, kOffB2 = kOffW2 + kMlpH * kMlpH,
+              kOffW3 = kOffB2 + kMlpH, kOffB3 = kOffW3 + kMlpH, kMlpParams = kOffB3 + 1;
+
+struct MlpState {
+  float* P = nullptr;  // parameters
+  float* G = nullptr;  // gradients
+  float* M = nullptr;  // Adam first moments
+  float* V = nullptr;  // Adam second moments
+  int step = 0;
+  bool trained = false;
+  double y_mean = 0.0, y_std = 1.0;  // standardisation of log seconds
+  // scratch for a batch of samples
+  float *X = nullptr, *T = nullptr, *Y = nullptr, *H1 = nullptr, *H2 = nullptr, *loss = nullptr;
+  int cap = 0;
+};
+
+// ----------------------------------------------------------------- features
+// op one-hot (3), precision one-hot (4), n terms (4), batch (1), variant
+// one-hot (5), tile 16 (1), matrix cores (1), waves one-hot (3), bias-free
+// padding to kMlpIn.
+void mlp_features(int op, int n, int prec, int batch, const tla_plan& p, float* f) {
+  for (int i = 0; i < kMlpIn; ++i) f[i] = 0.f;
+  f[op] = 1.f;
+  f[3 + prec] = 1.f;
+  const float nn = (float)n;
+  f[7] = std::log2(std::max(nn, 1.f)) / 7.f;
+  f[8] = nn / 128.f;
+  f[9] = (nn / 128.f) * (nn / 128.f);
+  f[10] = (float)((n + p.tile - 1) / p.tile) / 16.f;
+  f[11] = std::log2((float)std::max(batch, 1)) / 16.f;
+  f[12 + std::min(p.variant, 4)] = 1.f;
+  f[17] = p.tile == 16 ? 1.f : 0.f;
+  f[18] = p.engine ? 1.f : 0.f;
+  f[19 + (p.waves == 1 ? 0 : (p.waves == 2 ? 1 : 2))] = 1.f;
+  f[22] = f[10] * f[10];
+  f[23] = (float)(p.waves) * f[10] / 4.f;
+}
+
+// ------------------------------------------------------------------ kernels
+// One workgroup (64 lanes = the 64 hidden units) per sample.
+__global__ __launch_bounds__(64) void k_mlp_forward(const float* __restrict__ P, const float* __restrict__ X,
+                                                    float* Y, float* H1, float* H2, int N) {
+  __shared__ float x[kMlpIn], h1[kMlpH];
+  const int s = blockIdx.x, u = threadIdx.x;
+  if (s >= N) return;
+  if (u < kMlpIn) x[u] = X[(size_t)s * kMlpIn + u];
+  __syncthreads();
+  float a = P[kOffB1 + u];
+  for (int k = 0; k < kMlpIn; ++k) a += P[kOffW1 + u * kMlpIn + k] * x[k];
+  a = a > 0.f ? a : 0.f;
+  h1[u] = a;
+  if (H1) H1[(size_t)s * kMlpH + u] = a;
+  __syncthreads();
+  float b = P[kOffB2 + u];
+  for (int k = 0; k < kMlpH; ++k) b += P[kOffW2 + u * kMlpH + k] * h1[k];
+  b = b > 0.f ? b : 0.f;
+  if (H2) H2[(size_t)s * kMlpH + u] = b;
+  float y = P[kOffW3 + u] * b;
+  for (int o = 32; o > 0; o >>= 1) y += __shfl_xor(y, o);
+  if (u == 0) Y[s] = y + P[kOffB3];
+}
+
+// Gradients of L = (1/N) sum_s (y_s - t_s)^2, accumulated into G with atomics
+// (G must be zero on entry); loss accumulated into *loss.
+__global__ __launch_bounds__(64) void k_mlp_backward(const float* __restrict__ P, const float* __restrict__ X,
+                                                     const float* __restrict__ T, const float* __restrict__ Y,
+                                                     const float* __restrict__ H1, const float* __restrict__ H2,
+                                                     float* G, float* loss, int N) {
+  __shared__ float x[kMlpIn], h1[kMlpH], d2[kMlpH];
+  const int s = blockIdx.x, u = threadIdx.x;
+  if (s >= N) return;
+  if (u < kMlpIn) x[u] = X[(size_t)s * kMlpIn + u];
+  h1[u] = H1[(size_t)s * kMlpH + u];
+  const float h2 = H2[(size_t)s * kMlpH + u];
+  const float r = Y[s] - T[s];
+  const float dy = 2.f * r / (float)N;
+  if (u == 0) {
+    atomicAdd(loss, r * r / (float)N);
+    atomicAdd(&G[kOffB3], dy);
+  }
+  atomicAdd(&G[kOffW3 + u], dy * h2);
+  const float dh2 = h2 > 0.f ? dy * P[kOffW3 + u] : 0.f;
+  d2[u] = dh2;
+  atomicAdd(&G[kOffB2 + u], dh2);
+  __syncthreads();
+  for (int k = 0; k < kMlpH; ++k) atomicAdd(&G[kOffW2 + u * kMlpH + k], dh2 * h1[k]);
+  // dh1[u] = sum_v W2[v][u] dh2[v], masked by the ReLU of unit u
+  float dh1 = 0.f;
+  for (int v = 0; v < kMlpH; ++v) dh1 += P[kOffW2 + v * kMlpH + u] * d2[v];
+  dh1 = h1[u] > 0.f ? dh1 : 0.f;
+  atomicAdd(&G[kOffB1 + u], dh1);
+  for (int k = 0; k < kMlpIn; ++k) atomicAdd(&G[kOffW1 + u * kMlpIn + k], dh1 * x[k]);
+}
+
+// Adam (Kingma & Ba 2015) with bias correction; step t >= 1.
+__global__ void k_mlp_adam(float* P, const float* G, float* M, float* V, int n, float lr, float b1, float b2,
+                           float eps, int t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = G[i];
+  const float m = b1 * M[i] + (1.f - b1) * g;
+  const float v = b2 * V[i] + (1.f - b2) * g * g;
+  M[i] = m;
+  V[i] = v;
+  const float mh = m / (1.f - powf(b1, (float)t));
+  const float vh = v / (1.f - powf(b2, (float)t));
+  P[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void k_fill_f32(float* p, int n, float v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------ host side
+static tla_status mlp_alloc(tla_ctx* h) {
+  if (h->mlp) return TLA_OK;
+  MlpState* m = new (std::nothrow) MlpState();
+  if (!m) return TLA_E_NOMEM;
+  const size_t b = kMlpParams * sizeof(float);
+  if (hipMalloc(&m->P, b) != hipSuccess || hipMalloc(&m->G, b) != hipSuccess || hipMalloc(&m->M, b) != hipSuccess ||
+      hipMalloc(&m->V, b) != hipSuccess || hipMalloc(&m->loss, sizeof(float)) != hipSuccess) {
+    delete m;
+    return TLA_E_NOMEM;
+  }
+  h->mlp = m;
+  return TLA_OK;
+}
+
+static tla_status mlp_reserve(MlpState* m, int N) {
+  if (N <= m->cap) return TLA_OK;
+  hipFree(m->X); hipFree(m->T); hipFree(m->Y); hipFree(m->H1); hipFree(m->H2);
+  m->X = m->T = m->Y = m->H1 = m->H2 = nullptr;
+  m->cap = 0;
+  if (hipMalloc(&m->X, (size_t)N * kMlpIn * sizeof(float)) != hipSuccess ||
+      hipMalloc(&m->T, (size_t)N * sizeof(float)) != hipSuccess || hipMalloc(&m->Y, (size_t)N * sizeof(float)) != hipSuccess ||
+      hipMalloc(&m->H1, (size_t)N * kMlpH * sizeof(float)) != hipSuccess ||
+      hipMalloc(&m->H2, (size_t)N * kMlpH * sizeof(float)) != hipSuccess)
+    return TLA_E_NOMEM;
+  m->cap = N;
+  return TLA_OK;
+}
+
+// He-style uniform initialisation from a SplitMix64 stream
+static void mlp_init_host(std::vector<float>& p, unsigned long long seed) {
+  p.assign(kMlpParams, 0.f);
+  auto next = [&]() {
+    seed += 0x9E3779B97F4A7C15ull;
+    unsigned long long z = seed;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-53;
+  };
+  const float a1 = std::sqrt(6.f / kMlpIn), a2 = std::sqrt(6.f / kMlpH);
+  for (int i = 0; i < kMlpH * kMlpIn; ++i) p[kOffW1 + i] = (float)((2 * next() - 1) * a1);
+  for (int i = 0; i < kMlpH * kMlpH; ++i) p[kOffW2 + i] = (float)((2 * next() - 1) * a2);
+  for (int i = 0; i < kMlpH; ++i) p[kOffW3 + i] = (float)((2 * next() - 1) * a2);
+}
+
+static tla_status mlp_fwd_bwd(tla_ctx* h, int N, bool backward) {
+  MlpState* m = h->mlp;
+  hipLaunchKernelGGL(k_mlp_forward, dim3(N), dim3(64), 0, h->stream, m->P, m->X, m->Y, m->H1, m->H2, N);
+  if (backward) {
+    hipLaunchKernelGGL(k_fill_f32, dim3((kMlpParams + 255) / 256), dim3(256), 0, h->stream, m->G, kMlpParams, 0.f);
+    hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(64), 0, h->stream, m->loss, 1, 0.f);
+    hipLaunchKernelGGL(k_mlp_backward, dim3(N), dim3(64), 0, h->stream, m->P, m->X, m->T, m->Y, m->H1, m->H2, m->G,
+                       m->loss, N);
+  }
+  return hipGetLastError() == hipSuccess ? TLA_OK : TLA_E_HIP;
+}
+
+static tla_status mlp_adam(tla_ctx* h, float lr) {
+  MlpState* m = h->mlp;
+  ++m->step;
+  hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, h->stream, m->P, m->G, m->M, m->V,
+                     kMlpParams, lr, 0.9f, 0.999f, 1e-8f, m->step);
+  return hipGetLastError() == hipSuccess ? TLA_OK : TLA_E_HIP;
+}
+
+static tla_status mlp_reset(tla_ctx* h, unsigned long long seed) {
+  std::vector<float> p;
+  mlp_init_host(p, seed);
+  MlpState* m = h->mlp;
+  if (hipMemcpy(m->P, p.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return TLA_E_HIP;
+  std::vector<float> z(kMlpParams, 0.f);
+  if (hipMemcpy(m->M, z.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->V, z.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+    return TLA_E_HIP;
+  m->step = 0;
+  return TLA_OK;
+}
+
+bool mlp_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* best) {
+  MlpState* m = h->mlp;
+  if (!m || !m->trained) return false;
+  const int nc = num_candidates(op);
+  if (mlp_reserve(m, nc) != TLA_OK) return false;
+  std::vector<float> X((size_t)nc * kMlpIn);
+  std::vector<tla_plan> plans(nc);
+  int usable = 0;
+  for (int c = 0; c < nc; ++c) {
+    tla_plan p;
+    candidate(op, c, &p);
+    size_t lds;
+    if (choose_placement(h, op, prec, p, (n + p.tile - 1) / p.tile, &lds) < 0) continue;
+    plans[usable] = p;
+    mlp_features(op, n, prec, batch, p, &X[(size_t)usable * kMlpIn]);
+    ++usable;
+  }
+  if (usable == 0) return false;
+  if (hipMemcpyAsync(m->X, X.data(), (size_t)usable * kMlpIn * sizeof(float), hipMemcpyHostToDevice, h->stream) !=
+      hipSuccess)
+    return false;
+  hipLaunchKernelGGL(k_mlp_forward, dim3(usable), dim3(64), 0, h->stream, m->P, m->X, m->Y, (float*)nullptr,
+                     (float*)nullptr, usable);
+  std::vector<float> Y(usable);
+  if (hipMemcpyAsync(Y.data(), m->Y, usable * sizeof(float), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return false;
+  const int arg = (int)(std::min_element(Y.begin(), Y.end()) - Y.begin());
+  *best = plans[arg];
+  return true;
+}
+
+void mlp_release(tla_ctx* h) {
+  MlpState* m = h->mlp;
+  if (!m) return;
+  hipFree(m->P); hipFree(m->G); hipFree(m->M); hipFree(m->V); hipFree(m->loss);
+  hipFree(m->X); hipFree(m->T); hipFree(m->Y); hipFree(m->H1); hipFree(m->H2);
+  delete m;
+  h->mlp = nullptr;
+}
+
 }  // namespace tla
+
+using namespace tla;
+
+// ---------------------------------------------------------------- C ABI
+extern "C" int tla_mlp_num_params(void) { return kMlpParams; }
+extern "C" int tla_mlp_num_features(void) { return kMlpIn; }
+
+extern "C" tla_status tla_mlp_features(tla_op op, int n, tla_prec prec, int batch, const tla_plan* plan, float* out) {
+  if (!plan || !out || op < 0 || op > 2 || prec < 0 || prec > 3) return TLA_E_ARG;
+  mlp_features(op, n, prec, batch, *plan, out);
+  return TLA_OK;
+}
+
+extern "C" tla_status tla_mlp_set_params(tla_handle h, const float* params) {
+  if (!h || !params) return TLA_E_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return TLA_E_HIP;
+  tla_status s = mlp_alloc(h);
+  if (s != TLA_OK) return s;
+  if (hipMemcpy(h->mlp->P, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return TLA_E_HIP;
+  std::vector<float> z(kMlpParams, 0.f);
+  hipMemcpy(h->mlp->M, z.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice);
+  hipMemcpy(h->mlp->V, z.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice);
+  h->mlp->step = 0;
+  return TLA_OK;
+}
+
+extern "C" tla_status tla_mlp_get_params(tla_handle h, float* params) {
+  if (!h || !params || !h->mlp) return TLA_E_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return TLA_E_HIP;
+  return hipMemcpy(params, h->mlp->P, kMlpParams * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess ? TLA_OK
+                                                                                                        : TLA_E_HIP;
+}
+
+// Loss and gradient of the current parameters on N samples (host arrays),
+// through the device forward and backward kernels.  Synchronous.
+extern "C" tla_status tla_mlp_forward_backward(tla_handle h, int N, const float* X, const float* T, float* loss,
+                                               float* grad, float* Y) {
+  if (!h || N < 1 || !X || !T || !h->mlp) return TLA_E_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return TLA_E_HIP;
+  MlpState* m = h->mlp;
+  tla_status s = mlp_reserve(m, N);
+  if (s != TLA_OK) return s;
+  if (hipMemcpy(m->X, X, (size_t)N * kMlpIn * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->T, T, (size_t)N * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+    return TLA_E_HIP;
+  s = mlp_fwd_bwd(h, N, true);
+  if (s != TLA_OK) return s;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return TLA_E_HIP;
+  if (loss && hipMemcpy(loss, m->loss, sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) return TLA_E_HIP;
+  if (grad && hipMemcpy(grad, m->G, kMlpParams * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) return TLA_E_HIP;
+  if (Y && hipMemcpy(Y, m->Y, N * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) return TLA_E_HIP;
+  return TLA_OK;
+}
+
+// One Adam step on the device with the given gradient (host array).
+extern "C" tla_status tla_mlp_adam_step(tla_handle h, const float* grad, float lr) {
+  if (!h || !grad || !h->mlp) return TLA_E_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return TLA_E_HIP;
+  if (hipMemcpy(h->mlp->G, grad, kMlpParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return TLA_E_HIP;
+  tla_status s = mlp_adam(h, lr);
+  if (s != TLA_OK) return s;
+  return hipStreamSynchronize(h->stream) == hipSuccess ? TLA_OK : TLA_E_HIP;
+}
+
+// Trains the cost model on every measurement in the tuning table whose n is
+// not excluded (exclude_mod > 0 leaves out n with n % exclude_mod == 0, the
+// held-out sizes of the regret test).  Full-batch Adam, `epochs` steps.
+extern "C" tla_status tla_mlp_train(tla_handle h, int epochs, float lr, unsigned long long seed, int exclude_mod,
+                                    float* final_loss) {
+  if (!h || epochs < 0 || !(lr > 0.f)) return TLA_E_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return TLA_E_HIP;
+  tla_status s = mlp_alloc(h);
+  if (s != TLA_OK) return s;
+  MlpState* m = h->mlp;
+  std::vector<float> X, T;
+  std::vector<double> ly;
+  for (const TuneRecord& r : h->records) {
+    if (exclude_mod > 0 && r.n % exclude_mod == 0) continue;
+    if (!(r.seconds > 0.0)) continue;
+    std::vector<float> f(kMlpIn);
+    mlp_features(r.op, r.n, r.prec, r.batch, r.plan, f.data());
+    X.insert(X.end(), f.begin(), f.end());
+    ly.push_back(std::log(r.seconds));
+  }
+  const int N = (int)ly.size();
+  if (N < 2) return TLA_E_ARG;
+  double mu = 0, sd = 0;
+  for (double v : ly) mu += v;
+  mu /= N;
+  for (double v : ly) sd += (v - mu) * (v - mu);
+  sd = std::sqrt(sd / N);
+  if (!(sd > 0)) sd = 1.0;
+  for (double v : ly) T.push_back((float)((v - mu) / sd));
+  m->y_mean = mu;
+  m->y_std = sd;
+  s = mlp_reserve(m, N);
+  if (s != TLA_OK) return s;
+  if (hipMemcpy(m->X, X.data(), X.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->T, T.data(), T.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+    return TLA_E_HIP;
+  s = mlp_reset(h, seed);
+  if (s != TLA_OK) return s;
+  for (int e = 0; e < epochs; ++e) {
+    s = mlp_fwd_bwd(h, N, true);
+    if (s != TLA_OK) return s;
+    s = mlp_adam(h, lr);
+    if (s != TLA_OK) return s;
+  }
+  s = mlp_fwd_bwd(h, N, true);
+  if (s != TLA_OK) return s;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return TLA_E_HIP;
+  if (final_loss && hipMemcpy(final_loss, m->loss, sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+    return TLA_E_HIP;
+  m->trained = true;
+  return TLA_OK;
+}
+
+// Predicted seconds per launch of `plan` (one forward launch).
+extern "C" tla_status tla_mlp_predict(tla_handle h, tla_op op, int n, tla_prec prec, int batch, const tla_plan* plan,
+                                      double* seconds) {
+  if (!h || !plan || !seconds || !h->mlp) return TLA_E_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return TLA_E_HIP;
+  MlpState* m = h->mlp;
+  if (mlp_reserve(m, 1) != TLA_OK) return TLA_E_NOMEM;
+  float f[kMlpIn];
+  mlp_features(op, n, prec, batch, *plan, f);
+  if (hipMemcpy(m->X, f, sizeof f, hipMemcpyHostToDevice) != hipSuccess) return TLA_E_HIP;
+  hipLaunchKernelGGL(k_mlp_forward, dim3(1), dim3(64), 0, h->stream, m->P, m->X, m->Y, (float*)nullptr,
+                     (float*)nullptr, 1);
+  float y = 0.f;
+  if (hipStreamSynchronize(h->stream) != hipSuccess ||
+      hipMemcpy(&y, m->Y, sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+    return TLA_E_HIP;
+  *seconds = std::exp(m->y_mean + m->y_std * (double)y);
+  return TLA_OK;
+}
+
+extern "C" tla_status tla_mlp_save(tla_handle h, const char* path) {
+  if (!h || !path || !h->mlp) return TLA_E_ARG;
+  std::vector<float> p(kMlpParams);
+  if (tla_mlp_get_params(h, p.data()) != TLA_OK) return TLA_E_HIP;
+  FILE* f = fopen(path, "w");
+  if (!f) return TLA_E_ARG;
+  fprintf(f, "tla-mlp %d %d %.17g %.17g\n", kMlpIn, kMlpParams, h->mlp->y_mean, h->mlp->y_std);
+  for (float v : p) fprintf(f, "%.9g\n", v);
+  fclose(f);
+  return TLA_OK;
+}
+
+extern "C" tla_status tla_mlp_load(tla_handle h, const char* path) {
+  if (!h || !path) return TLA_E_ARG;
+  FILE* f = fopen(path, "r");
+  if (!f) return TLA_E_ARG;
+  int nin = 0, np = 0;
+  double mu = 0, sd = 1;
+  if (fscanf(f, "tla-mlp %d %d %lg %lg", &nin, &np, &mu, &sd) != 4 || nin != kMlpIn || np != kMlpParams) {
+    fclose(f);
+    return TLA_E_ARG;
+  }
+  std::vector<float> p(kMlpParams);
+  for (int i = 0; i < kMlpParams; ++i)
+    if (fscanf(f, "%g", &p[i]) != 1) { fclose(f); return TLA_E_ARG; }
+  fclose(f);
+  tla_status s = tla_mlp_set_params(h, p.data());
+  if (s != TLA_OK) return s;
+  h->mlp->y_mean = mu;
+  h->mlp->y_std = sd;
+  h->mlp->trained = true;
+  return TLA_OK;
+}
