@@ -44,7 +44,22 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=384)
     p.add_argument("--ops", default="potrf,trsyl,trlyap")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     return p.parse_args()
+
+
+def copy_calibration(mib):
+    """A plain copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}))
 
 
 def flops(op, n):
@@ -194,6 +209,9 @@ def cpu_baseline(orc, benches_host, sample):
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a design "
                                    "note, not a measured path", "n_gpus": a.gpus}))

@@ -129,8 +129,11 @@ tla_status tla_ragged_batched(tla_handle h, tla_prec prec, int batch, int n_max,
  * variant = blocked-algorithm variant (op specific, see tla_variant_name),
  * tile    = diagonal-block size (8 or 16),
  * engine  = 0 vector ALU tile updates, 1 matrix-core (MFMA) tile updates,
- * waves   = wavefronts per instance (1, 2 or 4). */
-typedef struct { int variant, tile, engine, waves; } tla_plan;
+ * waves   = wavefronts per instance (1, 2 or 4),
+ * place   = 0 stage the triangular coefficients in LDS when they fit,
+ *           1 read them through the caches (smaller LDS footprint, more
+ *           instances per compute unit); Sylvester and Lyapunov only. */
+typedef struct { int variant, tile, engine, waves, place; } tla_plan;
 
 /* Which picker chooses plans: the measured tuning table, the MLP cost model
  * (the table remains the fallback), or the built-in default. */

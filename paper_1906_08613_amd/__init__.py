@@ -47,13 +47,14 @@ class TlaError(RuntimeError):
 
 class Plan(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int), ("tile", ctypes.c_int), ("engine", ctypes.c_int),
-                ("waves", ctypes.c_int)]
+                ("waves", ctypes.c_int), ("place", ctypes.c_int)]
 
     def __repr__(self):
-        return f"Plan(variant={self.variant}, tile={self.tile}, engine={self.engine}, waves={self.waves})"
+        return (f"Plan(variant={self.variant}, tile={self.tile}, engine={self.engine}, waves={self.waves}, "
+                f"place={self.place})")
 
     def astuple(self):
-        return (self.variant, self.tile, self.engine, self.waves)
+        return (self.variant, self.tile, self.engine, self.waves, self.place)
 
 
 class Desc(ctypes.Structure):
@@ -188,7 +189,7 @@ class Handle:
     # ------------------------------------------------------------- plans
     def set_plan(self, op, prec, plan=None):
         if plan is None:
-            p = Plan(-1, 16, 1, 4)
+            p = Plan(-1, 16, 1, 4, 0)
         else:
             p = Plan(*plan) if not isinstance(plan, Plan) else plan
         check(lib().tla_set_plan(self.h, OPS.get(op, op), _prec(prec), ctypes.byref(p)), "tla_set_plan")

@@ -34,13 +34,19 @@ bool plan_valid(int op, const tla_plan& p) {
   if (p.engine != 0 && p.engine != 1) return false;
   if (p.tile == 8 && p.engine == 1) return false;
   if (p.waves != 1 && p.waves != 2 && p.waves != 4) return false;
+  if (p.place != 0 && p.place != 1) return false;
+  if (op == TLA_POTRF && p.place != 0) return false;
   return true;
 }
 
-// candidates: variant x (tile, engine) x waves
-int num_candidates(int op) { return num_variants(op) * kNumTE * kNumNW; }
+// candidates: variant x (tile, engine) x waves x coefficient placement
+static int num_places(int op) { return op == TLA_POTRF ? 1 : 2; }
+int num_candidates(int op) { return num_variants(op) * kNumTE * kNumNW * num_places(op); }
 bool candidate(int op, int i, tla_plan* p) {
   if (i < 0 || i >= num_candidates(op)) return false;
+  const int np = num_places(op);
+  p->place = i % np;
+  i /= np;
   const int nwi = i % kNumNW, te = (i / kNumNW) % kNumTE, var = i / (kNumNW * kNumTE);
   p->variant = var;
   p->tile = te_tile(te);
@@ -56,6 +62,7 @@ tla_plan default_plan(int op, int n, int prec) {
   p.tile = 16;
   p.engine = 1;
   p.waves = n <= 16 ? 1 : (n <= 32 ? 2 : 4);
+  p.place = 0;
   (void)op;
   return p;
 }
@@ -194,7 +201,7 @@ static KFn kernel_for(int op, int prec, const tla_plan& p, int pl) {
 // First placement whose LDS fits: returns -1 when none does.
 int choose_placement(tla_ctx* h, int op, int prec, const tla_plan& p, int ntmax, size_t* lds) {
   const int last = prec == TLA_F64 ? (op == TLA_POTRF ? 0 : 1) : (op == TLA_POTRF ? 2 : 2);
-  for (int pl = 0; pl <= last; ++pl) {
+  for (int pl = (op == TLA_POTRF ? 0 : p.place); pl <= last; ++pl) {
     if (prec != TLA_F64 && op == TLA_POTRF && pl == 1) continue;
     const size_t b = lds_bytes(op, prec, p.tile, p.waves, ntmax, pl);
     if (b <= (size_t)h->lds_limit) { *lds = b; return pl; }

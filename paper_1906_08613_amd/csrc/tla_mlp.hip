@@ -40,8 +40,8 @@ struct MlpState {
 
 // ----------------------------------------------------------------- features
 // op one-hot (3), precision one-hot (4), n terms (4), batch (1), variant
-// one-hot (5), tile 16 (1), matrix cores (1), waves one-hot (3), bias-free
-// padding to kMlpIn.
+// one-hot (5), tile 16 (1), matrix cores (1), waves one-hot (3), tile count
+// squared (1), coefficients through the caches (1).
 void mlp_features(int op, int n, int prec, int batch, const tla_plan& p, float* f) {
   for (int i = 0; i < kMlpIn; ++i) f[i] = 0.f;
   f[op] = 1.f;
@@ -57,7 +57,7 @@ void mlp_features(int op, int n, int prec, int batch, const tla_plan& p, float* 
   f[18] = p.engine ? 1.f : 0.f;
   f[19 + (p.waves == 1 ? 0 : (p.waves == 2 ? 1 : 2))] = 1.f;
   f[22] = f[10] * f[10];
-  f[23] = (float)(p.waves) * f[10] / 4.f;
+  f[23] = p.place ? 1.f : 0.f;
 }
 
 // ------------------------------------------------------------------ kernels

@@ -181,6 +181,9 @@ struct Gemm<T, TB, ENG_VALU> {
 // i + j = s are finalised together and then subtract their contribution
 // from the elements below them in their column and right of them in their
 // row.  Elements with i >= ni or j >= nj (padding) are forced to zero.
+// One LDS fence per anti-diagonal: the values finalised for step s + 1 are
+// published at the end of step s, after this step's reads (the LDS serves a
+// wave in order, so the reads still see step s's values).
 template <class T, int TB, class VL, class VU>
 TLA_DI void tile_sylv(Tile<T, TB>& c, const VL& Lt, const VU& Ut, T* buf, int ni, int nj) {
   const int l = lane_id(), j = tcol<TB>(l);
@@ -193,128 +196,159 @@ TLA_DI void tile_sylv(Tile<T, TB>& c, const VL& Lt, const VU& Ut, T* buf, int ni
   for (int r = 0; r < E; ++r) {
     const int i = trow<T, TB>(l, r);
     rinv[r] = (i < ni && j < nj) ? T(1) / (Lt(i, i) + ujj) : T(0);
+    if (i + j == 0) {
+      const T x = c.v[r] * rinv[r];
+      c.v[r] = x;
+      colbuf[j] = x;
+      rowbuf[i] = x;
+    }
   }
 #pragma unroll 1
   for (int s = 0; s < 2 * TB - 1; ++s) {
+    const int k = s - j;
+    T lv[E], uv[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int i = trow<T, TB>(l, r);
-      if (i + j == s) {
+      const int k2 = s - i;
+      lv[r] = (k >= 0 && k < i) ? Lt(i, k) : T(0);
+      uv[r] = (k2 >= 0 && k2 < j) ? Ut(k2, j) : T(0);
+    }
+    wave_fence();
+    const T xc = (k >= 0 && k < TB) ? colbuf[j] : T(0);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = trow<T, TB>(l, r);
+      const int k2 = s - i;
+      const T xr = (k2 >= 0 && k2 < TB) ? rowbuf[i] : T(0);
+      c.v[r] -= lv[r] * xc;
+      c.v[r] -= xr * uv[r];
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = trow<T, TB>(l, r);
+      if (i + j == s + 1) {
         const T x = c.v[r] * rinv[r];
         c.v[r] = x;
         colbuf[j] = x;
         rowbuf[i] = x;
       }
     }
-    wave_fence();
-    const int k = s - j;
-    const T xc = colbuf[j];
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const int i = trow<T, TB>(l, r);
-      if (k >= 0 && k < i) c.v[r] -= Lt(i, k) * xc;
-      const int k2 = s - i;
-      if (k2 >= 0 && k2 < j) c.v[r] -= rowbuf[i] * Ut(k2, j);
-    }
-    wave_fence();
   }
+  wave_fence();
 }
 
 // Upper Cholesky of a diagonal tile held in c (only j >= i is used/valid):
 // unblocked right-looking.  Pivots of rows >= nv are padding (value 1).
 // The first failing pivot (<= 0 or NaN) is reported as base + k + 1 into
-// *info if *info is still 0.
+// *info if *info is still 0.  Row k of the partly updated tile is final
+// after step k - 1; its owners publish it, and after one fence every lane
+// forms the pivot and the scaled row entries it needs itself.
 template <class T, int TB>
 TLA_DI void tile_potf2(Tile<T, TB>& c, T* buf, int nv, int base, int* info) {
   const int l = lane_id(), j = tcol<TB>(l);
   constexpr int E = Tile<T, TB>::EPL;
-  T* diag = buf;        // diag[k] = x_kk
-  T* rowk = buf + TB;   // rowk[j] = x_kj of the current k
+  T* rowk = buf;   // rowk[j] = a_kj after the updates of steps < k
+#pragma unroll
+  for (int r = 0; r < E; ++r)
+    if (trow<T, TB>(l, r) == 0) rowk[j] = c.v[r];
 #pragma unroll 1
   for (int k = 0; k < TB; ++k) {
+    wave_fence();
+    const T p = rowk[k];
+    const T d = sqrt(p);
+    const T rd = T(1) / d;
+    const T xj = rowk[j] * rd;
+    if (l == 0 && !(p > T(0)) && k < nv && *info == 0) *info = base + k + 1;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int i = trow<T, TB>(l, r);
-      if (i == k && j == k) {
-        const T p = c.v[r];
-        if (!(p > T(0)) && k < nv && *info == 0) *info = base + k + 1;
-        const T d = sqrt(p);
-        c.v[r] = d;
-        diag[k] = d;
-        rowk[k] = d;
-      }
+      if (i == k) c.v[r] = (j == k) ? d : (j > k ? xj : c.v[r]);
+      else if (i > k && j >= i) c.v[r] -= (rowk[i] * rd) * xj;
     }
-    wave_fence();
+    // row k + 1 is now final: publish it (reads of rowk above came first)
 #pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const int i = trow<T, TB>(l, r);
-      if (i == k && j > k) {
-        const T x = c.v[r] / diag[k];
-        c.v[r] = x;
-        rowk[j] = x;
-      }
-    }
-    wave_fence();
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const int i = trow<T, TB>(l, r);
-      if (i > k && j >= i) c.v[r] -= rowk[i] * rowk[j];
-    }
-    wave_fence();
+    for (int r = 0; r < E; ++r)
+      if (trow<T, TB>(l, r) == k + 1) rowk[j] = c.v[r];
   }
+  wave_fence();
 }
 
 // Left solve with the transpose of an upper-triangular diagonal tile:
-// c := Xd^{-T} c  (forward substitution down every column).
+// c := Xd^{-T} c  (forward substitution down every column).  Row k of the
+// solution is final after step k - 1 and is published then.
 template <class T, int TB, class VX>
 TLA_DI void tile_trsm_ut(Tile<T, TB>& c, const VX& Xd, T* buf) {
   const int l = lane_id(), j = tcol<TB>(l);
   constexpr int E = Tile<T, TB>::EPL;
+  T xrow[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int i = trow<T, TB>(l, r);
+    if (i == 0) {
+      c.v[r] = c.v[r] / Xd(0, 0);
+      buf[j] = c.v[r];
+    }
+  }
 #pragma unroll 1
-  for (int k = 0; k < TB; ++k) {
+  for (int k = 0; k < TB - 1; ++k) {
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-      if (trow<T, TB>(l, r) == k) {
-        const T y = c.v[r] / Xd(k, k);
-        c.v[r] = y;
-        buf[j] = y;
-      }
+      const int i = trow<T, TB>(l, r);
+      xrow[r] = i > k ? Xd(k, i) : T(0);
     }
+    const T dk1 = Xd(k + 1, k + 1);
     wave_fence();
     const T y = buf[j];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int i = trow<T, TB>(l, r);
-      if (i > k) c.v[r] -= Xd(k, i) * y;
+      if (i > k) c.v[r] -= xrow[r] * y;
+      if (i == k + 1) {
+        c.v[r] = c.v[r] / dk1;
+        buf[j] = c.v[r];
+      }
     }
-    wave_fence();
   }
+  wave_fence();
 }
 
 // Right solve with an upper-triangular diagonal tile: c := c Xd^{-1}
-// (substitution along every row, left to right).
+// (substitution along every row, left to right); column k of the solution
+// is published when it becomes final.
 template <class T, int TB, class VX>
 TLA_DI void tile_trsm_right_u(Tile<T, TB>& c, const VX& Xd, T* buf) {
   const int l = lane_id(), j = tcol<TB>(l);
   constexpr int E = Tile<T, TB>::EPL;
+  if (j == 0) {
+    const T d0 = Xd(0, 0);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      c.v[r] = c.v[r] / d0;
+      buf[trow<T, TB>(l, r)] = c.v[r];
+    }
+  }
 #pragma unroll 1
-  for (int k = 0; k < TB; ++k) {
-    if (j == k) {
+  for (int k = 0; k < TB - 1; ++k) {
+    const T u = j > k ? Xd(k, j) : T(0);
+    const T dk1 = Xd(k + 1, k + 1);
+    wave_fence();
+    T y[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) y[r] = buf[trow<T, TB>(l, r)];
+    if (j > k) {
+#pragma unroll
+      for (int r = 0; r < E; ++r) c.v[r] -= y[r] * u;
+    }
+    if (j == k + 1) {
 #pragma unroll
       for (int r = 0; r < E; ++r) {
-        const T y = c.v[r] / Xd(k, k);
-        c.v[r] = y;
-        buf[trow<T, TB>(l, r)] = y;
+        c.v[r] = c.v[r] / dk1;
+        buf[trow<T, TB>(l, r)] = c.v[r];
       }
     }
-    wave_fence();
-    if (j > k) {
-      const T u = Xd(k, j);
-#pragma unroll
-      for (int r = 0; r < E; ++r) c.v[r] -= buf[trow<T, TB>(l, r)] * u;
-    }
-    wave_fence();
   }
+  wave_fence();
 }
 
 }  // namespace tla

@@ -206,10 +206,10 @@ extern "C" tla_status tla_save_table(tla_handle h, const char* path) {
   if (!h || !path) return TLA_E_ARG;
   FILE* f = fopen(path, "w");
   if (!f) return TLA_E_ARG;
-  fprintf(f, "# op n prec batch variant tile engine waves seconds\n");
+  fprintf(f, "# op n prec batch variant tile engine waves place seconds\n");
   for (auto& r : h->records)
-    fprintf(f, "%d %d %d %d %d %d %d %d %.9e\n", r.op, r.n, r.prec, r.batch, r.plan.variant, r.plan.tile,
-            r.plan.engine, r.plan.waves, r.seconds);
+    fprintf(f, "%d %d %d %d %d %d %d %d %d %.9e\n", r.op, r.n, r.prec, r.batch, r.plan.variant, r.plan.tile,
+            r.plan.engine, r.plan.waves, r.plan.place, r.seconds);
   fclose(f);
   return TLA_OK;
 }
@@ -224,8 +224,8 @@ extern "C" tla_status tla_load_table(tla_handle h, const char* path) {
   while (fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
     TuneRecord r;
-    if (sscanf(line, "%d %d %d %d %d %d %d %d %lf", &r.op, &r.n, &r.prec, &r.batch, &r.plan.variant, &r.plan.tile,
-               &r.plan.engine, &r.plan.waves, &r.seconds) != 9)
+    if (sscanf(line, "%d %d %d %d %d %d %d %d %d %lf", &r.op, &r.n, &r.prec, &r.batch, &r.plan.variant,
+               &r.plan.tile, &r.plan.engine, &r.plan.waves, &r.plan.place, &r.seconds) != 10)
       continue;
     if (!plan_valid(r.op, r.plan)) continue;
     h->records.push_back(r);

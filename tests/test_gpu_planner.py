@@ -59,12 +59,13 @@ def test_mlp_adam_step_matches_oracle(h):
 
 def synthetic_table(path, fn):
     """Tuning records with times from a known function of (op, n, plan)."""
-    lines = ["# op n prec batch variant tile engine waves seconds"]
+    lines = ["# op n prec batch variant tile engine waves place seconds"]
     for op in range(3):
         for n in range(4, 129, 4):
             for i in range(tla.num_candidates(op)):
                 p = tla.candidate(op, i)
-                lines.append(f"{op} {n} 0 1024 {p.variant} {p.tile} {p.engine} {p.waves} {fn(op, n, p):.9e}")
+                lines.append(f"{op} {n} 0 1024 {p.variant} {p.tile} {p.engine} {p.waves} {p.place} "
+                             f"{fn(op, n, p):.9e}")
     open(path, "w").write("\n".join(lines) + "\n")
 
 
@@ -72,7 +73,7 @@ def toy_time(op, n, p):
     base = (n ** 3) * (1 + op) * 1e-9
     eng = 0.6 if p.engine else 1.0
     waves = {1: 1.5, 2: 1.0, 4: 0.8 if n > 48 else 1.3}[p.waves]
-    return base * eng * waves * (1 + 0.1 * p.variant) + 1e-5
+    return base * eng * waves * (1 + 0.1 * p.variant) * (0.9 if p.place else 1.0) + 1e-5
 
 
 def test_table_argmin_rule(h, tmp_path):
@@ -113,7 +114,7 @@ def test_mlp_regret_on_measured_timings(h, tmp_path):
     rec = np.loadtxt(path, comments="#")
     times = {}
     for r in rec:
-        times[(int(r[0]), int(r[1]), (int(r[4]), int(r[5]), int(r[6]), int(r[7])))] = r[8]
+        times[(int(r[0]), int(r[1]), (int(r[4]), int(r[5]), int(r[6]), int(r[7]), int(r[8])))] = r[9]
 
     def regret(handle, mode):
         handle.set_picker(mode)
