@@ -151,7 +151,7 @@ namespace tla {
 size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int pl) {
   const size_t np = (size_t)ntmax * tb;
   const size_t mat8 = np * (np + 1) * 8, mat4 = np * (np + 1) * 4;
-  const size_t scr = (size_t)nw * 4 * tb * 8 + 16 + 8 * (nw + 4);
+  const size_t scr = (size_t)nw * wave_scratch(tb) * 8 + 16 + 8 * (nw + 4);
   if (prec == TLA_F64) {
     if (op == TLA_POTRF) return mat8 + scr;
     if (op == TLA_TRSYL) return mat8 * (pl == 0 ? 3 : 1) + scr;

@@ -4,6 +4,10 @@
 
 namespace tla {
 
+// Per-wave LDS scratch of the tile solvers, in elements: two broadcast
+// vectors of TB plus two staged TB x TB coefficient tiles (ld TB + 1).
+__host__ __device__ constexpr int wave_scratch(int tb) { return 2 * tb + 2 * tb * (tb + 1); }
+
 // Arguments of every batched kernel (device pointers, passed by value).
 //   potrf : c = A (in/out), ldc
 //   trsyl : a = L, b = U, c = C -> X

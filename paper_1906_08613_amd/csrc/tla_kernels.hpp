@@ -27,13 +27,16 @@ struct GView {
   TLA_DI T operator()(int i, int j) const {
     const int r = tr ? r0 + j : r0 + i;
     const int c = tr ? c0 + i : c0 + j;
-    if (r >= n || c >= n) return T(0);
+    const bool in = r < n && c < n;
+    int rr = r < n ? r : n - 1, cc = c < n ? c : n - 1;
     if (tri == 2 || tri == -2) {  // symmetric, stored in the upper (2) or lower (-2) triangle
-      const bool swap = tri == 2 ? r > c : r < c;
-      return swap ? T(p[c + (size_t)r * ld]) : T(p[r + (size_t)c * ld]);
+      const bool swap = tri == 2 ? rr > cc : rr < cc;
+      if (swap) { const int t = rr; rr = cc; cc = t; }
     }
-    const bool ok = tri == 0 || (tri < 0 ? r >= c : r <= c);
-    return ok ? T(p[r + (size_t)c * ld]) : T(0);
+    // unconditional load from a clamped address, then select
+    const double raw = to_gbl(p)[rr + (size_t)cc * ld];
+    const bool ok = in && (tri == 0 || tri == 2 || tri == -2 || (tri < 0 ? r >= c : r <= c));
+    return ok ? T(raw) : T(0);
   }
   TLA_DI GView sub(int i0, int j0) const {
     GView v = *this;
@@ -55,19 +58,25 @@ TLA_DI GView<T> gview(const double* p, int ld, int n, int tri) { return GView<T>
 // off-diagonal entries twice when `sym` (a symmetric matrix given by one
 // triangle).
 template <class T, int NW>
-TLA_DI double ingest(T* W, int ldw, int np, const double* G, int ldg, int n, int part, T pad, bool sym = false) {
+TLA_DI double ingest(T* Wg, int ldw, int np, const double* Gg, int ldg, int n, int part, T pad, bool sym = false) {
   constexpr int U = 8;
   const int w = wave_id(), l = lane_id();
+  lds_t<T>* W = to_lds(Wg);
+  const gbl_t<double>* G = to_gbl(Gg);
   double ss = 0.0;
   for (int i0 = 0; i0 < np; i0 += 64) {
     const int i = i0 + l;
+    const int ic = i < n ? i : n - 1;
     for (int jb = w; jb < np; jb += NW * U) {
       double v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
+        // unconditional load from a clamped (always valid) address, then select
         const int j = jb + u * NW;
+        const int jc = j < n ? j : n - 1;
+        const double raw = G[ic + (size_t)jc * ldg];
         const bool keep = i < n && j < n && (part == 0 || (part < 0 ? i >= j : i <= j));
-        v[u] = keep ? G[i + (size_t)j * ldg] : 0.0;
+        v[u] = keep ? raw : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -85,8 +94,10 @@ TLA_DI double ingest(T* W, int ldw, int np, const double* G, int ldg, int n, int
 
 // Mirrors the lower triangle of an np x np LDS matrix into its upper triangle
 // (call between barriers).
-template <class T>
-TLA_DI void mirror_lower(T* W, int ldw, int np) {
+template <class T, bool LDS = true>
+TLA_DI void mirror_lower(T* Wg, int ldw, int np) {
+  const View<T, LDS> Wv = xcolmajor<!LDS>(Wg, ldw);
+  auto* W = Wv.p;
   for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
     const int j = e / np, i = e - j * np;
     if (i < j) W[i + j * ldw] = W[j + i * ldw];
@@ -94,10 +105,13 @@ TLA_DI void mirror_lower(T* W, int ldw, int np) {
 }
 
 // Writes the n x n result back: part 0 full, +1 upper triangle only,
-// 2 symmetric from the lower triangle.
-template <class T, int NW>
-TLA_DI void egress(double* G, int ldg, int n, const T* W, int ldw, int part) {
+// 2 symmetric from the lower triangle.  The source is in LDS unless !LDS.
+template <class T, int NW, bool LDS = true>
+TLA_DI void egress(double* Gg, int ldg, int n, const T* Wg, int ldw, int part) {
   const int w = wave_id(), l = lane_id();
+  const View<T, LDS> Wv = xcolmajor<!LDS>(const_cast<T*>(Wg), ldw);
+  const auto* W = Wv.p;
+  gbl_t<double>* G = to_gbl(Gg);
   for (int j = w; j < n; j += NW) {
     for (int i = l; i < n; i += 64) {
       if (part == 1 && i > j) continue;
@@ -108,8 +122,8 @@ TLA_DI void egress(double* G, int ldg, int n, const T* W, int ldw, int part) {
 }
 
 // first zero denominator d_ij = a_i + b_j (column-major index + 1) into *info
-template <class VA, class VB>
-TLA_DI void scan_zero_denoms(const VA& A, const VB& B, int n, bool lower_only, int* info) {
+template <class VA, class VB, class IP>
+TLA_DI void scan_zero_denoms(const VA& A, const VB& B, int n, bool lower_only, IP info) {
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int j = e / n, i = e - j * n;
     if (lower_only && i < j) continue;
@@ -180,7 +194,7 @@ __host__ __device__ inline size_t lds_mat_bytes(int ntmax, int tb, int elem) {
   return np * (np + 1) * elem;
 }
 __host__ __device__ inline size_t lds_scratch_bytes(int nw, int tb, int elem) {
-  return (size_t)nw * 4 * tb * elem + 16;
+  return (size_t)nw * wave_scratch(tb) * elem + 16;
 }
 
 // ================================================================ FP64
@@ -192,11 +206,11 @@ TLA_DI void potrf_f64_body(const KArgs& g, const Inst& in, unsigned char* smem) 
   const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
   double* A = reinterpret_cast<double*>(smem);
   double* wb = A + (size_t)g.ntmax * TB * (g.ntmax * TB + 1);
-  int* s_info = reinterpret_cast<int*>(wb + NW * 4 * TB);
+  int* s_info = reinterpret_cast<int*>(wb + NW * wave_scratch(TB));
   if (threadIdx.x == 0) *s_info = 0;
   ingest<double, NW>(A, ld, np, in.c, in.ldc, n, +1, 1.0);
   __syncthreads();
-  Ctx<double> cx{n, nt, wb + wave_id() * 4 * TB, s_info};
+  Ctx<double> cx{n, nt, to_lds(wb + wave_id() * wave_scratch(TB)), to_lds(s_info)};
   potrf_blocked<double, TB, ENG, NW, VAR>(colmajor(A, ld), cx);
   __syncthreads();
   egress<double, NW>(in.c, in.ldc, n, A, ld, 1);
@@ -223,7 +237,7 @@ TLA_DI void trsyl_f64_body(const KArgs& g, const Inst& in, unsigned char* smem) 
   double* Ls = X + mat;
   double* Us = Ls + mat;
   double* wb = LU_LDS ? Us + mat : Ls;
-  int* s_info = reinterpret_cast<int*>(wb + NW * 4 * TB);
+  int* s_info = reinterpret_cast<int*>(wb + NW * wave_scratch(TB));
   if (threadIdx.x == 0) *s_info = INT_MAX;
   ingest<double, NW>(X, ld, np, in.c, in.ldc, n, 0, 0.0);
   if constexpr (LU_LDS) {
@@ -231,7 +245,7 @@ TLA_DI void trsyl_f64_body(const KArgs& g, const Inst& in, unsigned char* smem) 
     ingest<double, NW>(Us, ld, np, in.b, in.ldb, n, +1, 0.0);
   }
   __syncthreads();
-  Ctx<double> cx{n, nt, wb + wave_id() * 4 * TB, s_info};
+  Ctx<double> cx{n, nt, to_lds(wb + wave_id() * wave_scratch(TB)), to_lds(s_info)};
   if constexpr (LU_LDS) {
     scan_zero_denoms(colmajor(Ls, ld), colmajor(Us, ld), n, false, s_info);
     trsyl_blocked<double, TB, ENG, NW, VAR>(colmajor(X, ld), colmajor(Ls, ld), colmajor(Us, ld), cx);
@@ -265,14 +279,14 @@ TLA_DI void trlyap_f64_body(const KArgs& g, const Inst& in, unsigned char* smem)
   double* X = reinterpret_cast<double*>(smem);
   double* Ls = X + mat;
   double* wb = LU_LDS ? Ls + mat : Ls;
-  int* s_info = reinterpret_cast<int*>(wb + NW * 4 * TB);
+  int* s_info = reinterpret_cast<int*>(wb + NW * wave_scratch(TB));
   if (threadIdx.x == 0) *s_info = INT_MAX;
   ingest<double, NW>(X, ld, np, in.c, in.ldc, n, -1, 0.0);
   if constexpr (LU_LDS) ingest<double, NW>(Ls, ld, np, in.a, in.lda, n, -1, 0.0);
   __syncthreads();
   mirror_lower(X, ld, np);
   __syncthreads();
-  Ctx<double> cx{n, nt, wb + wave_id() * 4 * TB, s_info};
+  Ctx<double> cx{n, nt, to_lds(wb + wave_id() * wave_scratch(TB)), to_lds(s_info)};
   if constexpr (LU_LDS) {
     scan_zero_denoms(colmajor(Ls, ld), colmajor(Ls, ld), n, true, s_info);
     trlyap_blocked<double, TB, ENG, NW, VAR>(colmajor(X, ld), colmajor(Ls, ld), cx);

@@ -101,9 +101,9 @@ TLA_DI MixedLds carve(unsigned char* smem, const KArgs& g, int naux) {
   m.A1 = m.W + mat;
   m.A2 = m.A1 + (naux >= 1 ? mat : 0);
   float* after = m.A2 + (naux >= 2 ? mat : 0);
-  m.wb = after;
-  m.red = reinterpret_cast<double*>(m.wb + NW * 4 * TB + 4);
-  m.red = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(m.red) + 7) & ~uintptr_t(7));
+  // scratch sized for FP64 (the fallback solve reuses it), 8-byte aligned
+  m.wb = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(after) + 7) & ~uintptr_t(7));
+  m.red = reinterpret_cast<double*>(m.wb) + NW * wave_scratch(TB);
   m.ired = reinterpret_cast<int*>(m.red + NW + 1);
   m.info = m.ired + 1;
   return m;
@@ -166,7 +166,7 @@ TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
   bad |= block_or<NW>(lo_zero | bad, m.ired);
   st.flags |= bad;
   const int info0 = *m.info == INT_MAX ? 0 : *m.info;
-  Ctx<float> cx{n, nt, m.wb + wave_id() * 4 * TB, m.info};
+  Ctx<float> cx{n, nt, to_lds(m.wb + wave_id() * wave_scratch(TB)), to_lds(m.info)};
   if (info0 == 0 && !bad) {
     // low-precision solve of the full system
     if constexpr (LU_LDS) trsyl_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), colmajor(m.A1, ld), colmajor(m.A2, ld), cx);
@@ -179,7 +179,7 @@ TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
       for (;;) {
         // R = C - L Xd - Xd U (FP64), into W; squared norms of R and Xd
         double sr = 0.0, sx = 0.0;
-        const View<double> Xv = colmajor(m.Xd, ld);
+        const auto Xv = xcolmajor<XG>(m.Xd, ld);
         for (int t = wave_id(); t < nt * nt; t += NW) {
           const int I = t / nt, J = t - I * nt;
           Tile<double, TB> c, x;
@@ -216,13 +216,12 @@ TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
     // FP64 solve of the instance (fallback or breakdown)
     ingest<double, NW>(m.Xd, ld, np, Cg, ldc, n, 0, 0.0);
     __syncthreads();
-    Ctx<double> cd{n, nt, reinterpret_cast<double*>(m.W), m.info};
-    cd.wbuf = reinterpret_cast<double*>(m.W) + wave_id() * 4 * TB;
+    Ctx<double> cd{n, nt, to_lds(reinterpret_cast<double*>(m.wb) + wave_id() * wave_scratch(TB)), to_lds(m.info)};
     constexpr int ENG64 = ENG == ENG_VALU ? ENG_VALU : E64;
-    trsyl_blocked<double, TB, ENG64, NW, VAR>(colmajor(m.Xd, ld), L64, U64, cd);
+    trsyl_blocked<double, TB, ENG64, NW, VAR>(xcolmajor<XG>(m.Xd, ld), L64, U64, cd);
     __syncthreads();
   }
-  if (info0 == 0 && !(XG && fb)) egress<double, NW>(Cg, ldc, n, m.Xd, ld, 0);
+  if (info0 == 0 && !(XG && fb)) egress<double, NW, !XG>(Cg, ldc, n, m.Xd, ld, 0);
   if (threadIdx.x == 0) *in.info = info0;
   write_stat(in, st);
 }
@@ -274,7 +273,7 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
   bad |= block_or<NW>(lo_zero | bad, m.ired);
   st.flags |= bad;
   const int info0 = *m.info == INT_MAX ? 0 : *m.info;
-  Ctx<float> cx{n, nt, m.wb + wave_id() * 4 * TB, m.info};
+  Ctx<float> cx{n, nt, to_lds(m.wb + wave_id() * wave_scratch(TB)), to_lds(m.info)};
   if (info0 == 0 && !bad) {
     if constexpr (LU_LDS) trlyap_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), colmajor(m.A1, ld), cx);
     else trlyap_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), gview<float>(Lg, ldl, n, -1), cx);
@@ -288,7 +287,7 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
       for (;;) {
         // R = S - L Xd - Xd L^T on the lower tiles (Xd is kept symmetric)
         double sr = 0.0, sx = 0.0;
-        const View<double> Xv = colmajor(m.Xd, ld);
+        const auto Xv = xcolmajor<XG>(m.Xd, ld);
         for (int t = wave_id(); t < nt * nt; t += NW) {
           const int I = t / nt, J = t - I * nt;
           if (I < J) continue;
@@ -321,7 +320,7 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
           if (i >= j) m.Xd[i + j * ld] += double(m.W[i + j * ld]);
         }
         __syncthreads();
-        mirror_lower(m.Xd, ld, np);
+        mirror_lower<double, !XG>(m.Xd, ld, np);
         ++st.it;
         __syncthreads();
       }
@@ -332,14 +331,14 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
   if (!XG && fb) {
     ingest<double, NW>(m.Xd, ld, np, Sg, lds, n, -1, 0.0);
     __syncthreads();
-    mirror_lower(m.Xd, ld, np);
+    mirror_lower<double, !XG>(m.Xd, ld, np);
     __syncthreads();
-    Ctx<double> cd{n, nt, reinterpret_cast<double*>(m.W) + wave_id() * 4 * TB, m.info};
+    Ctx<double> cd{n, nt, to_lds(reinterpret_cast<double*>(m.wb) + wave_id() * wave_scratch(TB)), to_lds(m.info)};
     constexpr int ENG64 = ENG == ENG_VALU ? ENG_VALU : E64;
-    trlyap_blocked<double, TB, ENG64, NW, VAR>(colmajor(m.Xd, ld), L64, cd);
+    trlyap_blocked<double, TB, ENG64, NW, VAR>(xcolmajor<XG>(m.Xd, ld), L64, cd);
     __syncthreads();
   }
-  if (info0 == 0 && !(XG && fb)) egress<double, NW>(Sg, lds, n, m.Xd, ld, 2);
+  if (info0 == 0 && !(XG && fb)) egress<double, NW, !XG>(Sg, lds, n, m.Xd, ld, 2);
   if (threadIdx.x == 0) *in.info = info0;
   write_stat(in, st);
 }
@@ -354,8 +353,8 @@ __global__ __launch_bounds__(NW * 64) void k_trlyap_mixed(KArgs g) {
 // Tile solves of the Newton correction, FP32 (X32 upper factor in aux):
 //   M1 = X^{-T} R   column tile by column tile (forward substitution down)
 //   M  = M1 X^{-1}  row tile by row tile (substitution to the right)
-template <class T, int TB, int ENG, int NW>
-TLA_DI void newton_correction(const View<T>& Wv, const View<T>& Xv, const View<double>& Xd, int nt, T* wbuf) {
+template <class T, int TB, int ENG, int NW, class VW, class VXd>
+TLA_DI void newton_correction(const VW& Wv, const VW& Xv, const VXd& Xd, int nt, lds_t<T>* wbuf) {
   typedef Gemm<T, TB, ENG> G;
   const int w = wave_id();
   for (int J = w; J < nt; J += NW) {
@@ -417,7 +416,7 @@ TLA_DI void potrf_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
 
   const double na = sqrt(block_sum<NW>(ingest<float, NW>(m.W, ld, np, Ag, lda, n, +1, 1.0f, true), m.red));
   int bad = (na - na != 0.0) ? TLA_STAT_NONFINITE : 0;
-  Ctx<float> cx{n, nt, m.wb + wave_id() * 4 * TB, m.info};
+  Ctx<float> cx{n, nt, to_lds(m.wb + wave_id() * wave_scratch(TB)), to_lds(m.info)};
   if (!bad) {
     potrf_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), cx);
     __syncthreads();
@@ -430,7 +429,7 @@ TLA_DI void potrf_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
       m.Xd[i + j * ld] = (i <= j && j < n) ? double(m.W[i + j * ld]) : 0.0;
     }
     __syncthreads();
-    const View<double> Xv = colmajor(m.Xd, ld);
+    const auto Xv = xcolmajor<XG>(m.Xd, ld);
     for (;;) {
       // R = A - Xd^T Xd, symmetric: upper tiles computed, mirrored into W
       double sr = 0.0;
@@ -459,7 +458,7 @@ TLA_DI void potrf_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
         m.A1[i + j * ld] = i < n && j < n ? float(m.Xd[i + j * ld]) : (i == j ? 1.0f : 0.0f);
       }
       __syncthreads();
-      newton_correction<float, TB, ENG, NW>(colmajor(m.W, ld), colmajor(m.A1, ld), Xv, nt, m.wb + wave_id() * 4 * TB);
+      newton_correction<float, TB, ENG, NW>(colmajor(m.W, ld), colmajor(m.A1, ld), Xv, nt, to_lds(m.wb + wave_id() * wave_scratch(TB)));
       ++st.it;
       __syncthreads();
     }
@@ -471,13 +470,13 @@ TLA_DI void potrf_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
     if (threadIdx.x == 0) *m.info = 0;
     ingest<double, NW>(m.Xd, ld, np, Ag, lda, n, +1, 1.0);
     __syncthreads();
-    Ctx<double> cd{n, nt, reinterpret_cast<double*>(m.W) + wave_id() * 4 * TB, m.info};
+    Ctx<double> cd{n, nt, to_lds(reinterpret_cast<double*>(m.wb) + wave_id() * wave_scratch(TB)), to_lds(m.info)};
     constexpr int ENG64 = ENG == ENG_VALU ? ENG_VALU : E64;
-    potrf_blocked<double, TB, ENG64, NW, VAR>(colmajor(m.Xd, ld), cd);
+    potrf_blocked<double, TB, ENG64, NW, VAR>(xcolmajor<XG>(m.Xd, ld), cd);
     __syncthreads();
     info0 = *m.info;
   }
-  if (!(XG && fb)) egress<double, NW>(Ag, lda, n, m.Xd, ld, 1);
+  if (!(XG && fb)) egress<double, NW, !XG>(Ag, lda, n, m.Xd, ld, 1);
   if (threadIdx.x == 0) *in.info = info0;
   write_stat(in, st);
 }

@@ -22,10 +22,10 @@ namespace tla {
 // Per-workgroup context handed to the drivers.
 template <class T>
 struct Ctx {
-  int n;      // order of this instance
-  int nt;     // number of tiles per dimension, ceil(n / TB)
-  T* wbuf;    // per-wave LDS scratch (this wave's slice)
-  int* info;  // LDS cell for the instance's info (first failure wins)
+  int n;              // order of this instance
+  int nt;             // number of tiles per dimension, ceil(n / TB)
+  lds_t<T>* wbuf;     // per-wave LDS scratch (this wave's slice)
+  lds_t<int>* info;   // LDS cell for the instance's info (first failure wins)
 };
 
 // ======================================================= Cholesky X^T X = A
@@ -38,16 +38,16 @@ struct Ctx {
 //            update A11 -= A01^T A01, factor A11.
 enum { CHOL_RL = 0, CHOL_LL = 1, CHOL_BD = 2, CHOL_NVAR = 3 };
 
-template <class T, int TB, int ENG, int NW>
-TLA_DI void chol_diag(const View<T>& A, const Ctx<T>& cx, int K) {
+template <class T, int TB, int ENG, int NW, class VA>
+TLA_DI void chol_diag(const VA& A, const Ctx<T>& cx, int K) {
   Tile<T, TB> c;
   tload(c, A.sub(K * TB, K * TB));
   tile_potf2<T, TB>(c, cx.wbuf, cx.n - K * TB, K * TB, cx.info);
   tstore(c, A.sub(K * TB, K * TB));
 }
 
-template <class T, int TB, int ENG, int NW, int VAR>
-TLA_DI void potrf_blocked(const View<T>& A, const Ctx<T>& cx) {
+template <class T, int TB, int ENG, int NW, int VAR, class VA>
+TLA_DI void potrf_blocked(const VA& A, const Ctx<T>& cx) {
   const int w = wave_id(), nt = cx.nt;
   typedef Gemm<T, TB, ENG> G;
   if constexpr (VAR == CHOL_RL) {
@@ -131,8 +131,8 @@ TLA_DI void syl_tile_solve(Tile<T, TB>& c, const VL& L, const VU& U, const Ctx<T
   tile_sylv<T, TB>(c, L.sub(I * TB, I * TB), U.sub(J * TB, J * TB), cx.wbuf, cx.n - I * TB, cx.n - J * TB);
 }
 
-template <class T, int TB, int ENG, int NW, int VAR, class VL, class VU>
-TLA_DI void trsyl_blocked(const View<T>& X, const VL& L, const VU& U, const Ctx<T>& cx) {
+template <class T, int TB, int ENG, int NW, int VAR, class VX, class VL, class VU>
+TLA_DI void trsyl_blocked(const VX& X, const VL& L, const VU& U, const Ctx<T>& cx) {
   const int w = wave_id(), nt = cx.nt;
   typedef Gemm<T, TB, ENG> G;
   if constexpr (VAR == SYL_WF) {
@@ -232,8 +232,8 @@ TLA_DI void trsyl_blocked(const View<T>& X, const VL& L, const VU& U, const Ctx<
 //           below it, then the symmetric rank-2b update of the trailing part.
 enum { LYA_WF = 0, LYA_RL = 1, LYA_RE = 2, LYA_NVAR = 3 };
 
-template <class T, int TB, class VL>
-TLA_DI void lya_tile_solve(Tile<T, TB>& c, const View<T>& X, const VL& L, const Ctx<T>& cx, int I, int J) {
+template <class T, int TB, class VX, class VL>
+TLA_DI void lya_tile_solve(Tile<T, TB>& c, const VX& X, const VL& L, const Ctx<T>& cx, int I, int J) {
   tile_sylv<T, TB>(c, L.sub(I * TB, I * TB), L.sub(J * TB, J * TB).t(), cx.wbuf, cx.n - I * TB, cx.n - J * TB);
   if (I == J) {
     // store the lower triangle into both halves: the tile becomes exactly symmetric
@@ -253,8 +253,8 @@ TLA_DI void lya_tile_solve(Tile<T, TB>& c, const View<T>& X, const VL& L, const 
 }
 
 // column-side lazy update: c -= sum_{K in [k0,k1)} L_IK X~_KJ, X~_KJ = X_KJ (K >= J) or X_JK^T
-template <class T, int TB, int ENG, class VL>
-TLA_DI void lya_colside(Tile<T, TB>& c, const View<T>& X, const VL& L, int I, int J, int k0, int k1) {
+template <class T, int TB, int ENG, class VX, class VL>
+TLA_DI void lya_colside(Tile<T, TB>& c, const VX& X, const VL& L, int I, int J, int k0, int k1) {
   typedef Gemm<T, TB, ENG> G;
   for (int K = k0; K < k1; ++K) {
     if (K >= J) G::sub(c, L.sub(I * TB, K * TB), X.sub(K * TB, J * TB));
@@ -262,14 +262,14 @@ TLA_DI void lya_colside(Tile<T, TB>& c, const View<T>& X, const VL& L, int I, in
   }
 }
 // row-side lazy update: c -= sum_{K in [k0,k1)} X_IK L_JK^T
-template <class T, int TB, int ENG, class VL>
-TLA_DI void lya_rowside(Tile<T, TB>& c, const View<T>& X, const VL& L, int I, int J, int k0, int k1) {
+template <class T, int TB, int ENG, class VX, class VL>
+TLA_DI void lya_rowside(Tile<T, TB>& c, const VX& X, const VL& L, int I, int J, int k0, int k1) {
   typedef Gemm<T, TB, ENG> G;
   for (int K = k0; K < k1; ++K) G::sub(c, X.sub(I * TB, K * TB), L.sub(J * TB, K * TB).t());
 }
 
-template <class T, int TB, int ENG, int NW, int VAR, class VL>
-TLA_DI void trlyap_blocked(const View<T>& X, const VL& L, const Ctx<T>& cx) {
+template <class T, int TB, int ENG, int NW, int VAR, class VX, class VL>
+TLA_DI void trlyap_blocked(const VX& X, const VL& L, const Ctx<T>& cx) {
   const int w = wave_id(), nt = cx.nt;
   typedef Gemm<T, TB, ENG> G;
   if constexpr (VAR == LYA_WF) {

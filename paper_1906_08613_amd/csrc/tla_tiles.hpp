@@ -17,6 +17,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+#include "tla_internal.h"
+
 namespace tla {
 
 #define TLA_DI __device__ __forceinline__
@@ -37,19 +41,43 @@ TLA_DI int wave_id() { return threadIdx.x >> 6; }
 TLA_DI void wave_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 // --------------------------------------------------------------- views
+// LDS-qualified element type: accesses through it compile to ds_read /
+// ds_write rather than flat (generic) memory instructions.
+template <class T>
+using lds_t = __attribute__((address_space(3))) T;
+template <class T>
+TLA_DI lds_t<T>* to_lds(T* p) { return (lds_t<T>*)p; }
+// global-memory-qualified element type (global_load / global_store)
+template <class T>
+using gbl_t = __attribute__((address_space(1))) T;
+template <class T>
+TLA_DI gbl_t<T>* to_gbl(T* p) { return (gbl_t<T>*)p; }
+template <class T>
+TLA_DI const gbl_t<T>* to_gbl(const T* p) { return (const gbl_t<T>*)p; }
+
 // Strided matrix view: element (i, j) at p[i*rs + j*cs].  Column-major
 // storage with leading dimension ld is (rs, cs) = (1, ld); t() transposes.
-template <class T>
+// LDS = true for matrices in LDS, false for global memory.
+template <class T, bool LDS = true>
 struct View {
-  T* p;
+  using P = std::conditional_t<LDS, lds_t<T>*, gbl_t<T>*>;
+  P p;
   int rs, cs;
   TLA_DI T operator()(int i, int j) const { return p[i * rs + j * cs]; }
-  TLA_DI T& at(int i, int j) const { return p[i * rs + j * cs]; }
+  TLA_DI auto& at(int i, int j) const { return p[i * rs + j * cs]; }
   TLA_DI View sub(int i0, int j0) const { return View{p + i0 * rs + j0 * cs, rs, cs}; }
   TLA_DI View t() const { return View{p, cs, rs}; }
 };
 template <class T>
-TLA_DI View<T> colmajor(T* p, int ld) { return View<T>{p, 1, ld}; }
+TLA_DI View<T, true> colmajor(T* p, int ld) { return View<T, true>{to_lds(p), 1, ld}; }
+template <class T>
+TLA_DI View<T, false> gcolmajor(T* p, int ld) { return View<T, false>{to_gbl(p), 1, ld}; }
+// column-major view in LDS or (XG) in global memory
+template <bool XG, class T>
+TLA_DI View<T, !XG> xcolmajor(T* p, int ld) {
+  if constexpr (XG) return gcolmajor(p, ld);
+  else return colmajor(p, ld);
+}
 
 // ----------------------------------------------------------- fragments
 template <class T> struct Frag;
@@ -91,8 +119,8 @@ TLA_DI void tload(Tile<T, TB>& c, const V& M) {
 #pragma unroll
   for (int r = 0; r < Tile<T, TB>::EPL; ++r) c.v[r] = M(trow<T, TB>(l, r), j);
 }
-template <class T, int TB>
-TLA_DI void tstore(const Tile<T, TB>& c, const View<T>& M) {
+template <class T, int TB, class V>
+TLA_DI void tstore(const Tile<T, TB>& c, const V& M) {
   const int l = lane_id(), j = tcol<TB>(l);
 #pragma unroll
   for (int r = 0; r < Tile<T, TB>::EPL; ++r) M.at(trow<T, TB>(l, r), j) = c.v[r];
@@ -181,46 +209,64 @@ struct Gemm<T, TB, ENG_VALU> {
 // i + j = s are finalised together and then subtract their contribution
 // from the elements below them in their column and right of them in their
 // row.  Elements with i >= ni or j >= nj (padding) are forced to zero.
-// One LDS fence per anti-diagonal: the values finalised for step s + 1 are
-// published at the end of step s, after this step's reads (the LDS serves a
-// wave in order, so the reads still see step s's values).
+//
+// The strictly triangular parts of Lt and Ut are first staged in the wave's
+// scratch and the broadcast vectors are zeroed, so that the update of every
+// step needs no test: a coefficient outside the strict triangle is zero, and
+// a broadcast value not yet produced is zero.  One LDS fence per
+// anti-diagonal: values finalised for step s + 1 are published at the end of
+// step s, after this step's reads (the LDS serves a wave in order).
 template <class T, int TB, class VL, class VU>
-TLA_DI void tile_sylv(Tile<T, TB>& c, const VL& Lt, const VU& Ut, T* buf, int ni, int nj) {
+TLA_DI void tile_sylv(Tile<T, TB>& c, const VL& Lt, const VU& Ut, lds_t<T>* buf, int ni, int nj) {
   const int l = lane_id(), j = tcol<TB>(l);
   constexpr int E = Tile<T, TB>::EPL;
-  T* colbuf = buf;        // colbuf[j] = element finalised in column j this step
-  T* rowbuf = buf + TB;   // rowbuf[i] = element finalised in row i this step
+  constexpr int LD = TB + 1;
+  lds_t<T>* colbuf = buf;              // colbuf[j] = element finalised in column j this step
+  lds_t<T>* rowbuf = buf + TB;         // rowbuf[i] = element finalised in row i this step
+  lds_t<T>* Ls = buf + 2 * TB;         // strictly lower part of Lt
+  lds_t<T>* Us = Ls + TB * LD;         // strictly upper part of Ut
   T rinv[E];
   const T ujj = Ut(j, j);
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int i = trow<T, TB>(l, r);
+    const T lv = Lt(i, j), uv = Ut(i, j);
+    Ls[i + j * LD] = i > j ? lv : T(0);
+    Us[i + j * LD] = i < j ? uv : T(0);
     rinv[r] = (i < ni && j < nj) ? T(1) / (Lt(i, i) + ujj) : T(0);
-    if (i + j == 0) {
+  }
+  if (l < TB) {
+    colbuf[l] = T(0);
+    rowbuf[l] = T(0);
+  }
+  wave_fence();
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    if (trow<T, TB>(l, r) + j == 0) {
       const T x = c.v[r] * rinv[r];
       c.v[r] = x;
-      colbuf[j] = x;
-      rowbuf[i] = x;
+      colbuf[0] = x;
+      rowbuf[0] = x;
     }
   }
-#pragma unroll 1
+#pragma unroll 2
   for (int s = 0; s < 2 * TB - 1; ++s) {
-    const int k = s - j;
+    int k = s - j;
+    k = k < 0 ? 0 : (k > TB - 1 ? TB - 1 : k);
     T lv[E], uv[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int i = trow<T, TB>(l, r);
-      const int k2 = s - i;
-      lv[r] = (k >= 0 && k < i) ? Lt(i, k) : T(0);
-      uv[r] = (k2 >= 0 && k2 < j) ? Ut(k2, j) : T(0);
+      int k2 = s - i;
+      k2 = k2 < 0 ? 0 : (k2 > TB - 1 ? TB - 1 : k2);
+      lv[r] = Ls[i + k * LD];
+      uv[r] = Us[k2 + j * LD];
     }
     wave_fence();
-    const T xc = (k >= 0 && k < TB) ? colbuf[j] : T(0);
+    const T xc = colbuf[j];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-      const int i = trow<T, TB>(l, r);
-      const int k2 = s - i;
-      const T xr = (k2 >= 0 && k2 < TB) ? rowbuf[i] : T(0);
+      const T xr = rowbuf[trow<T, TB>(l, r)];
       c.v[r] -= lv[r] * xc;
       c.v[r] -= xr * uv[r];
     }
@@ -245,10 +291,10 @@ TLA_DI void tile_sylv(Tile<T, TB>& c, const VL& Lt, const VU& Ut, T* buf, int ni
 // after step k - 1; its owners publish it, and after one fence every lane
 // forms the pivot and the scaled row entries it needs itself.
 template <class T, int TB>
-TLA_DI void tile_potf2(Tile<T, TB>& c, T* buf, int nv, int base, int* info) {
+TLA_DI void tile_potf2(Tile<T, TB>& c, lds_t<T>* buf, int nv, int base, lds_t<int>* info) {
   const int l = lane_id(), j = tcol<TB>(l);
   constexpr int E = Tile<T, TB>::EPL;
-  T* rowk = buf;   // rowk[j] = a_kj after the updates of steps < k
+  lds_t<T>* rowk = buf;   // rowk[j] = a_kj after the updates of steps < k
 #pragma unroll
   for (int r = 0; r < E; ++r)
     if (trow<T, TB>(l, r) == 0) rowk[j] = c.v[r];
@@ -278,7 +324,7 @@ TLA_DI void tile_potf2(Tile<T, TB>& c, T* buf, int nv, int base, int* info) {
 // c := Xd^{-T} c  (forward substitution down every column).  Row k of the
 // solution is final after step k - 1 and is published then.
 template <class T, int TB, class VX>
-TLA_DI void tile_trsm_ut(Tile<T, TB>& c, const VX& Xd, T* buf) {
+TLA_DI void tile_trsm_ut(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) {
   const int l = lane_id(), j = tcol<TB>(l);
   constexpr int E = Tile<T, TB>::EPL;
   T xrow[E];
@@ -295,7 +341,8 @@ TLA_DI void tile_trsm_ut(Tile<T, TB>& c, const VX& Xd, T* buf) {
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int i = trow<T, TB>(l, r);
-      xrow[r] = i > k ? Xd(k, i) : T(0);
+      const T raw = Xd(k, i);
+      xrow[r] = i > k ? raw : T(0);
     }
     const T dk1 = Xd(k + 1, k + 1);
     wave_fence();
@@ -317,7 +364,7 @@ TLA_DI void tile_trsm_ut(Tile<T, TB>& c, const VX& Xd, T* buf) {
 // (substitution along every row, left to right); column k of the solution
 // is published when it becomes final.
 template <class T, int TB, class VX>
-TLA_DI void tile_trsm_right_u(Tile<T, TB>& c, const VX& Xd, T* buf) {
+TLA_DI void tile_trsm_right_u(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) {
   const int l = lane_id(), j = tcol<TB>(l);
   constexpr int E = Tile<T, TB>::EPL;
   if (j == 0) {
@@ -330,7 +377,8 @@ TLA_DI void tile_trsm_right_u(Tile<T, TB>& c, const VX& Xd, T* buf) {
   }
 #pragma unroll 1
   for (int k = 0; k < TB - 1; ++k) {
-    const T u = j > k ? Xd(k, j) : T(0);
+    const T uraw = Xd(k, j);
+    const T u = j > k ? uraw : T(0);
     const T dk1 = Xd(k + 1, k + 1);
     wave_fence();
     T y[E];
