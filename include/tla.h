@@ -132,7 +132,10 @@ tla_status tla_ragged_batched(tla_handle h, tla_prec prec, int batch, int n_max,
  * waves   = wavefronts per instance (1, 2 or 4),
  * place   = 0 stage the triangular coefficients in LDS when they fit,
  *           1 read them through the caches (smaller LDS footprint, more
- *           instances per compute unit); Sylvester and Lyapunov only. */
+ *           instances per compute unit; Sylvester and Lyapunov only),
+ *           2 (mixed precisions only) also keep the FP64 solution in the
+ *           handle's workspace; its FP64 fallback is then a second launch.
+ * The launch falls back to a larger place value when LDS does not fit. */
 typedef struct { int variant, tile, engine, waves, place; } tla_plan;
 
 /* Which picker chooses plans: the measured tuning table, the MLP cost model

@@ -34,18 +34,21 @@ bool plan_valid(int op, const tla_plan& p) {
   if (p.engine != 0 && p.engine != 1) return false;
   if (p.tile == 8 && p.engine == 1) return false;
   if (p.waves != 1 && p.waves != 2 && p.waves != 4) return false;
-  if (p.place != 0 && p.place != 1) return false;
-  if (op == TLA_POTRF && p.place != 0) return false;
+  // place 2 (FP64 solution in the workspace) only exists for the mixed kernels;
+  // the launcher reports it unsupported for FP64
+  if (p.place < 0 || p.place > 2) return false;
+  if (op == TLA_POTRF && p.place == 1) return false;
   return true;
 }
 
 // candidates: variant x (tile, engine) x waves x coefficient placement
-static int num_places(int op) { return op == TLA_POTRF ? 1 : 2; }
+static int num_places(int op) { return op == TLA_POTRF ? 2 : 3; }
 int num_candidates(int op) { return num_variants(op) * kNumTE * kNumNW * num_places(op); }
 bool candidate(int op, int i, tla_plan* p) {
   if (i < 0 || i >= num_candidates(op)) return false;
   const int np = num_places(op);
   p->place = i % np;
+  if (op == TLA_POTRF && p->place == 1) p->place = 2;  // potrf: 0 or 2
   i /= np;
   const int nwi = i % kNumNW, te = (i / kNumNW) % kNumTE, var = i / (kNumNW * kNumTE);
   p->variant = var;
@@ -200,8 +203,9 @@ static KFn kernel_for(int op, int prec, const tla_plan& p, int pl) {
 
 // First placement whose LDS fits: returns -1 when none does.
 int choose_placement(tla_ctx* h, int op, int prec, const tla_plan& p, int ntmax, size_t* lds) {
-  const int last = prec == TLA_F64 ? (op == TLA_POTRF ? 0 : 1) : (op == TLA_POTRF ? 2 : 2);
-  for (int pl = (op == TLA_POTRF ? 0 : p.place); pl <= last; ++pl) {
+  const int last = prec == TLA_F64 ? (op == TLA_POTRF ? 0 : 1) : 2;
+  if (p.place > last) return -1;
+  for (int pl = p.place; pl <= last; ++pl) {
     if (prec != TLA_F64 && op == TLA_POTRF && pl == 1) continue;
     const size_t b = lds_bytes(op, prec, p.tile, p.waves, ntmax, pl);
     if (b <= (size_t)h->lds_limit) { *lds = b; return pl; }
@@ -245,9 +249,11 @@ tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& 
   if (s != TLA_OK || !xg) return s;
   // second pass: FP64 solve of the instances the mixed kernel left unconverged
   size_t lds64 = 0;
-  const int pl64 = choose_placement(h, op, TLA_F64, p, a.ntmax, &lds64);
+  tla_plan p64 = p;
+  p64.place = op == TLA_POTRF ? 0 : (p.place > 1 ? 1 : p.place);
+  const int pl64 = choose_placement(h, op, TLA_F64, p64, a.ntmax, &lds64);
   if (pl64 < 0) return TLA_E_UNSUPPORTED;
-  KFn fb = kernel_for(op, TLA_F64, p, pl64);
+  KFn fb = kernel_for(op, TLA_F64, p64, pl64);
   if (!fb) return TLA_E_UNSUPPORTED;
   a.only_flagged = 1;
   return launch_one(h, fb, lds64, a.batch, p.waves, a);

@@ -36,8 +36,8 @@ def test_host_only_queries():
     import paper_1906_08613_amd as tla
     if not os.path.exists(tla.LIB_PATH):
         pytest.skip("libtla.so not built")
-    assert tla.num_candidates("potrf") == 27
-    assert tla.num_candidates("trsyl") == 90      # 5 variants x 3 tile/engine x 3 waves x 2 placements
+    assert tla.num_candidates("potrf") == 54      # 3 variants x 3 tile/engine x 3 waves x 2 placements
+    assert tla.num_candidates("trsyl") == 135     # 5 variants x 3 tile/engine x 3 waves x 3 placements
     assert tla.variant_name("trsyl", 0) == "tile-wavefront"
     assert tla.lib().tla_status_string(4).decode() == "unsupported"
     # a null handle is rejected before any device work
