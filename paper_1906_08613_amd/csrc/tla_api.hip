@@ -223,6 +223,15 @@ static tla_status launch_one(tla_ctx* h, KFn fn, size_t lds, int grid, int waves
 
 tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& a0) {
   KArgs a = a0;
+  if (a.n_max > kMaxN) {
+    // large sizes: FP64 in place over global memory, variant from the plan
+    if (prec != TLA_F64) return TLA_E_UNSUPPORTED;
+    KFn fn = large_kernel(op, p.variant);
+    if (!fn) return TLA_E_UNSUPPORTED;
+    a.ntmax = (a.n_max + 15) / 16;
+    a.only_flagged = 0;
+    return launch_one(h, fn, large_lds_bytes(), a.batch, large_waves(), a);
+  }
   a.ntmax = (a.n_max + p.tile - 1) / p.tile;
   if (a.ntmax < 1) a.ntmax = 1;
   a.tau = h->tau;
@@ -274,7 +283,7 @@ static tla_status common_checks(tla_handle h, tla_prec prec, int batch, int n_ma
   if (!h) return TLA_E_ARG;
   if (batch < 0 || n_max < 0) return TLA_E_ARG;
   if (prec < TLA_F64 || prec > TLA_MIXED_BF16) return TLA_E_ARG;
-  if (n_max > tla::kMaxN) return TLA_E_UNSUPPORTED;
+  if (n_max > tla::kMaxLargeN) return TLA_E_UNSUPPORTED;
   return TLA_OK;
 }
 

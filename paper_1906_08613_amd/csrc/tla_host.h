@@ -11,7 +11,8 @@
 
 namespace tla {
 
-constexpr int kMaxN = 128;  // largest n of the per-instance (LDS-resident) kernels
+constexpr int kMaxN = 128;        // largest n of the LDS-resident kernels (and of ragged batches)
+constexpr int kMaxLargeN = 4096;  // largest n of the in-place global-memory kernels
 
 struct TuneRecord {
   int op, n, prec, batch;

@@ -396,7 +396,7 @@ TLA_DI void newton_correction(const VW& Wv, const VW& Xv, const VXd& Xd, int nt,
 #pragma unroll
     for (int r = 0; r < Tile<T, TB>::EPL; ++r) {
       const int i = trow<T, TB>(l, r);
-      if (I * TB + i <= J * TB + j) Xd.at(I * TB + i, J * TB + j) -= double(c.v[r]);  // c holds -E
+      if (I * TB + i <= J * TB + j) Xd.store(I * TB + i, J * TB + j, Xd(I * TB + i, J * TB + j) - double(c.v[r]));  // c holds -E
     }
   }
 }

@@ -27,3 +27,11 @@ KFn potrf_mixed_kernel(int prec, int var, int te, int nwi, int placement);
 KFn trsyl_mixed_kernel(int prec, int var, int te, int nwi, int placement);
 KFn trlyap_mixed_kernel(int prec, int var, int te, int nwi, int placement);
 }  // namespace tla
+
+namespace tla {
+// Large sizes (n above the LDS-resident maximum): in-place kernels over
+// global memory, FP64, one per variant; 16 waves per instance.
+KFn large_kernel(int op, int var);
+size_t large_lds_bytes();
+int large_waves();
+}  // namespace tla

@@ -242,11 +242,11 @@ TLA_DI void lya_tile_solve(Tile<T, TB>& c, const VX& X, const VL& L, const Ctx<T
     for (int r = 0; r < Tile<T, TB>::EPL; ++r) {
       const int i = trow<T, TB>(l, r);
       if (i >= j) {
-        X.at(I * TB + i, J * TB + j) = c.v[r];
-        X.at(J * TB + j, I * TB + i) = c.v[r];
+        X.store(I * TB + i, J * TB + j, c.v[r]);
+        X.store(J * TB + j, I * TB + i, c.v[r]);
       }
     }
-    wave_fence();
+    X.fence();
   } else {
     tstore(c, X.sub(I * TB, J * TB));
   }

@@ -65,8 +65,14 @@ struct View {
   int rs, cs;
   TLA_DI T operator()(int i, int j) const { return p[i * rs + j * cs]; }
   TLA_DI auto& at(int i, int j) const { return p[i * rs + j * cs]; }
+  TLA_DI void store(int i, int j, T v) const { p[i * rs + j * cs] = v; }
   TLA_DI View sub(int i0, int j0) const { return View{p + i0 * rs + j0 * cs, rs, cs}; }
   TLA_DI View t() const { return View{p, cs, rs}; }
+  // Makes this wave's stores visible to its other lanes before they read:
+  // the LDS serves a wave in order; global stores need to complete first.
+  TLA_DI void fence() const {
+    if constexpr (!LDS) __threadfence_block();
+  }
 };
 template <class T>
 TLA_DI View<T, true> colmajor(T* p, int ld) { return View<T, true>{to_lds(p), 1, ld}; }
@@ -123,7 +129,8 @@ template <class T, int TB, class V>
 TLA_DI void tstore(const Tile<T, TB>& c, const V& M) {
   const int l = lane_id(), j = tcol<TB>(l);
 #pragma unroll
-  for (int r = 0; r < Tile<T, TB>::EPL; ++r) M.at(trow<T, TB>(l, r), j) = c.v[r];
+  for (int r = 0; r < Tile<T, TB>::EPL; ++r) M.store(trow<T, TB>(l, r), j, c.v[r]);
+  M.fence();
 }
 template <class T, int TB>
 TLA_DI void tzero(Tile<T, TB>& c) {

@@ -138,7 +138,7 @@ tla_status time_plan(tla_ctx* h, Bench& B, int op, int prec, const tla_plan& p, 
 
 extern "C" tla_status tla_time_plan(tla_handle h, tla_op op, int n, tla_prec prec, int batch, const tla_plan* plan,
                                     int reps, double* seconds) {
-  if (!h || !plan || !seconds || n < 1 || n > kMaxN || batch < 1 || reps < 1 || op < 0 || op > 2) return TLA_E_ARG;
+  if (!h || !plan || !seconds || n < 1 || n > kMaxLargeN || batch < 1 || reps < 1 || op < 0 || op > 2) return TLA_E_ARG;
   if (!plan_valid(op, *plan)) return TLA_E_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return TLA_E_HIP;
   Bench B;
@@ -157,7 +157,7 @@ extern "C" tla_status tla_tune(tla_handle h, int n_ops, const int* ops, int n_ns
     if (op < 0 || op > 2) return TLA_E_ARG;
     for (int in = 0; in < n_ns; ++in) {
       const int n = ns[in];
-      if (n < 1 || n > kMaxN) return TLA_E_ARG;
+      if (n < 1 || n > kMaxLargeN) return TLA_E_ARG;
       Bench B;
       tla_status st = make_bench(B, op, n, batch, h->stream);
       if (st != TLA_OK) return st;

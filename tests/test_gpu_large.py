@@ -1,0 +1,91 @@
+"""Large sizes (n > 128): in-place FP64 kernels over global memory, every
+variant, against the oracle (relative Frobenius error 1e-12, inputs with
+condition numbers of about 2); the strict lower triangle of the Cholesky
+input must stay untouched."""
+import numpy as np
+import pytest
+
+import paper_1906_08613_amd as tla
+from paper_1906_08613_amd import inputs as I
+from tests.gpu_util import rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hd = tla.Handle(0)
+    yield hd
+    hd.close()
+
+
+@pytest.mark.parametrize("n", [129, 200, 256])
+def test_large_potrf_variants(h, orc, n):
+    A = I.potrf_problem("large", n, 2)
+    Xr, _ = orc.potrf_batch(A)
+    for v in range(3):
+        print(f"potrf n={n} v={v}", flush=True)
+        h.set_plan("potrf", "f64", (v, 16, 1, 4, 0))
+        host = np.triu(A) + np.tril(np.full((n, n), 3.5), -1)
+        dA = tla.to_device_cm(host)
+        ops = tla.potrf(h, dA)
+        torch.cuda.synchronize()
+        X = tla.from_device_cm(dA)
+        il = np.tril_indices(n, -1)
+        assert np.all(X[:, il[0], il[1]] == 3.5)
+        assert np.all(ops.info.cpu().numpy() == 0)
+        assert rel_err(np.triu(X), Xr).max() <= 1e-12, v
+    h.set_plan("potrf", "f64", None)
+
+
+@pytest.mark.parametrize("n", [129, 256])
+def test_large_trsyl_variants(h, orc, n):
+    L, U, C = I.trsyl_problem("large", n, 2)
+    Xr, _ = orc.trsyl_batch(L, U, C)
+    for v in range(5):
+        print(f"trsyl n={n} v={v}", flush=True)
+        h.set_plan("trsyl", "f64", (v, 16, 1, 4, 0))
+        dL, dU, dC = tla.to_device_cm(L), tla.to_device_cm(U), tla.to_device_cm(C)
+        ops = tla.trsyl(h, dL, dU, dC)
+        torch.cuda.synchronize()
+        assert np.all(ops.info.cpu().numpy() == 0)
+        assert rel_err(tla.from_device_cm(dC), Xr).max() <= 1e-12, v
+    h.set_plan("trsyl", "f64", None)
+
+
+@pytest.mark.parametrize("n", [129, 256])
+def test_large_trlyap_variants(h, orc, n):
+    L, S = I.trlyap_problem("large", n, 2)
+    Xr, _ = orc.trlyap_batch(L, S)
+    for v in range(3):
+        print(f"trlyap n={n} v={v}", flush=True)
+        h.set_plan("trlyap", "f64", (v, 16, 1, 4, 0))
+        dL, dS = tla.to_device_cm(L), tla.to_device_cm(np.tril(S))
+        ops = tla.trlyap(h, dL, dS)
+        torch.cuda.synchronize()
+        X = tla.from_device_cm(dS)
+        assert np.all(ops.info.cpu().numpy() == 0)
+        assert np.array_equal(X, np.swapaxes(X, 1, 2))
+        assert rel_err(X, Xr).max() <= 1e-12, v
+    h.set_plan("trlyap", "f64", None)
+
+
+def test_large_sampled_parity_512(h, orc):
+    # the largest sizes: a sample of instances through the oracle
+    n = 512
+    L, U, C = I.trsyl_problem("large512", n, 4)
+    dL, dU, dC = tla.to_device_cm(L), tla.to_device_cm(U), tla.to_device_cm(C)
+    tla.trsyl(h, dL, dU, dC)
+    torch.cuda.synchronize()
+    X = tla.from_device_cm(dC)
+    Xr, _ = orc.trsyl_batch(L[:1], U[:1], C[:1])
+    assert rel_err(X[:1], Xr).max() <= 1e-12
+    assert orc.eta_trsyl_batch(L, U, C, X).max() <= 1e-13
+    A = I.potrf_problem("large512", n, 4)
+    dA = tla.to_device_cm(np.triu(A))
+    tla.potrf(h, dA)
+    torch.cuda.synchronize()
+    assert orc.eta_potrf_batch(A, np.triu(tla.from_device_cm(dA))).max() <= 1e-13
