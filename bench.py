@@ -44,6 +44,10 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=384)
     p.add_argument("--ops", default="potrf,trsyl,trlyap")
+    p.add_argument("--workload", default="headline",
+                   choices=["headline", "potrf16", "sweep", "ragged", "large", "planner"],
+                   help="headline: the metric's configuration (default); the others print their own lines")
+    p.add_argument("--tune", action="store_true", help="autotune the headline configuration first")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     return p.parse_args()
@@ -207,6 +211,29 @@ def cpu_baseline(orc, benches_host, sample):
                       f"OpenMP over instances", "gflops": total_f / total_t / 1e9}
 
 
+def lib_hash():
+    """Digest of the built library: counter summaries are only reused for the same kernels."""
+    import hashlib
+    import paper_1906_08613_amd as tla
+    return hashlib.sha256(open(tla.LIB_PATH, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(kernel_op, prec, n, batch):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or
+    None when the summary is missing or the library has changed since."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    key = f"{kernel_op}/{prec}/n{n}/b{batch}"
+    e = d.get("entries", {}).get(key)
+    if not e or d.get("lib_hash") != lib_hash():
+        return None
+    return e["fetch_bytes"] + e["write_bytes"]
+
+
 def main():
     a = parse()
     if a.copy_calibration:
@@ -216,6 +243,10 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a design "
                                    "note, not a measured path", "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.workload != "headline":
+        import bench_workloads
+        bench_workloads.run(a)
+        return
     import torch
     import paper_1906_08613_amd as tla
     import oracle as orc
@@ -227,6 +258,8 @@ def main():
     h = tla.Handle(0)
     n, batch = a.n, a.batch
     ops = a.ops.split(",")
+    if a.tune:
+        h.tune(ops, [n], ["f64", a.prec], batch=batch, reps=3)
     copies = max(a.steps, a.warmup)
     hosts = [(op, make_inputs(op, n, batch, a.kappa)) for op in ops]
     benches = [OpBench(tla, torch, h, op, host, copies, a.prec) for op, host in hosts]
@@ -262,8 +295,10 @@ def main():
     dom = max(kern, key=kern.get)
     ach = batch * min_bytes(dom, n) / kern[dom] / 1e9
     res["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                       "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(dom, a.prec, n, batch),
+                       "algorithmic_bytes": batch * min_bytes(dom, n),
                        "fp64_tflops": batch * flops(dom, n) / kern[dom] / 1e12}
+    res["plans"] = {op: list(h.get_plan(op, n, a.prec, batch).astuple()) for op in ops}
     if not a.no_cpu:
         res["cpu_baseline"] = cpu_baseline(orc, hosts, min(a.cpu_sample, batch))
     print(json.dumps(res))

@@ -1,0 +1,311 @@
+"""The benchmark's secondary workloads (one JSON line each), run with
+python bench.py --workload {potrf16,sweep,ragged,large,planner}.
+
+potrf16 : FP64 Cholesky, 1024 instances at n = 16, replayed many times inside
+          one HIP graph (the batch is too small to fill the GPU by itself).
+sweep   : FP64 Sylvester and Lyapunov, n = 4, 8, ..., 128, 4096 instances each.
+ragged  : 65536 mixed instances (40% Cholesky, 30% Sylvester, 30% Lyapunov),
+          n uniform on {3..128}, FP64 and mixed, one graph-captured call.
+large   : 256 instances at n = 256, 512, 1024, FP64.
+planner : autotuner timings for n = 3..128 and the MLP trained on them;
+          regret of the learned picker on held-out n against the measured best.
+All inputs are synthetic and seeded (paper_1906_08613_amd.inputs); results
+are checked against the CPU oracle on a sample.
+"""
+from __future__ import annotations
+
+import json
+import time
+
+import numpy as np
+
+
+def _flops(op, n):
+    return n ** 3 / 3.0 if op == 0 else 2.0 * n ** 3
+
+
+def _bytes(op, n):
+    if op == 0:
+        return n * (n + 1) * 8
+    if op == 1:
+        return (n * (n + 1) + 2 * n * n) * 8
+    return (n * (n + 1) + n * n) * 8
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def potrf16(a):
+    import torch
+    import oracle
+    import paper_1906_08613_amd as tla
+    from paper_1906_08613_amd import inputs as I
+    n, batch, reps = 16, 1024, 200
+    h = tla.Handle(0)
+    A = I.potrf_problem("cfg0", n, batch)
+    dA = tla.to_device_cm(np.triu(A))
+    pristine = dA.clone()
+    ops = tla.Operands(n, dA)
+    # graph of `reps` launches on a side stream; restore copies are outside it
+    s = torch.cuda.Stream()
+    h.set_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        h.potrf_batched("f64", batch, n, ops.n, ops.ptrs[0], ops.lds[0], ops.info, ops.stat)  # warm-up
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(reps):
+                h.potrf_batched("f64", batch, n, ops.n, ops.ptrs[0], ops.lds[0], ops.info, ops.stat)
+    times = []
+    for _ in range(5):
+        dA.copy_(pristine)
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch)
+        e0.record(s)
+        g.replay()
+        e1.record(s)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3 / reps)
+    # one clean solve for the check
+    dA.copy_(pristine)
+    h.potrf_batched("f64", batch, n, ops.n, ops.ptrs[0], ops.lds[0], ops.info, ops.stat)
+    torch.cuda.synchronize()
+    X = np.triu(tla.from_device_cm(dA))
+    Xr, _ = oracle.potrf_batch(A[:64])
+    t = float(np.median(times))
+    t0 = time.perf_counter()
+    oracle.potrf_batch(A)
+    tc = time.perf_counter() - t0
+    print(json.dumps({"workload": "potrf f64 n=16 x1024 (graph of 200 launches)", "solves_per_s": batch / t,
+                      "gflops": batch * _flops(0, n) / t / 1e9, "gbs": batch * _bytes(0, n) / t / 1e9,
+                      "us_per_launch": t * 1e6,
+                      "fwd_err_max": float(oracle.forward_error(X[:64], Xr).max()),
+                      "cpu_oracle_solves_per_s": batch / tc, "cpu_threads": oracle.max_threads()}))
+
+
+def sweep(a):
+    import torch
+    import oracle
+    import paper_1906_08613_amd as tla
+    from paper_1906_08613_amd import inputs as I
+    h = tla.Handle(0)
+    batch = 4096
+    for opname, op in (("trsyl", 1), ("trlyap", 2)):
+        for n in range(4, 129, 4):
+            if op == 1:
+                L, U, C = I.trsyl_problem("cfg1", n, batch)
+                dL, dU, dC = tla.to_device_cm(L), tla.to_device_cm(U), tla.to_device_cm(C)
+                ops = tla.Operands(n, dL, dU, dC)
+                run = lambda: h.trsyl_batched("f64", batch, n, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1],
+                                              ops.lds[1], ops.ptrs[2], ops.lds[2], ops.info)
+                pristine, work = dC.clone(), dC
+            else:
+                L, S = I.trlyap_problem("cfg1", n, batch)
+                dL, dS = tla.to_device_cm(L), tla.to_device_cm(np.tril(S))
+                ops = tla.Operands(n, dL, dS)
+                run = lambda: h.trlyap_batched("f64", batch, n, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1],
+                                               ops.lds[1], ops.info)
+                pristine, work = dS.clone(), dS
+            ts = []
+            for _ in range(4):
+                work.copy_(pristine)
+                torch.cuda.synchronize()
+                e0, e1 = _events(torch)
+                e0.record()
+                run()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+            t = float(np.median(ts[1:]))
+            X = tla.from_device_cm(work)[:8]
+            if op == 1:
+                Xr, _ = oracle.trsyl_batch(L[:8], U[:8], C[:8])
+            else:
+                Xr, _ = oracle.trlyap_batch(L[:8], S[:8])
+            print(json.dumps({"workload": f"{opname} f64 n={n} x{batch}", "n": n,
+                              "solves_per_s": batch / t, "gflops": batch * _flops(op, n) / t / 1e9,
+                              "gbs": batch * _bytes(op, n) / t / 1e9, "ms": t * 1e3,
+                              "plan": list(h.get_plan(opname, n, "f64", batch).astuple()),
+                              "fwd_err_max": float(oracle.forward_error(X, Xr).max())}), flush=True)
+
+
+def _ragged_batch(tag, batch):
+    from paper_1906_08613_amd import inputs as I
+    ops, ns = I.ragged_mix(tag, batch)
+    mats = [None] * batch
+    for op in range(3):
+        for n in np.unique(ns[ops == op]):
+            idx = np.nonzero((ops == op) & (ns == n))[0]
+            n = int(n)
+            if op == 0:
+                A = I.potrf_problem(tag + "p", n, len(idx))
+                for k, b in enumerate(idx):
+                    mats[b] = (np.triu(A[k]),)
+            elif op == 1:
+                L, U, C = I.trsyl_problem(tag + "s", n, len(idx))
+                for k, b in enumerate(idx):
+                    mats[b] = (L[k], U[k], C[k])
+            else:
+                L, S = I.trlyap_problem(tag + "l", n, len(idx))
+                for k, b in enumerate(idx):
+                    mats[b] = (L[k], np.tril(S[k]))
+    return ops, ns, mats
+
+
+def ragged(a):
+    import torch
+    import oracle
+    import paper_1906_08613_amd as tla
+    batch = 65536
+    ops, ns, mats = _ragged_batch("cfg3", batch)
+    rb = tla.RaggedBatch(ops, mats)
+    pristine = rb.buf.clone()
+    h = tla.Handle(0)
+    flops = sum(_flops(int(o), int(n)) for o, n in zip(ops, ns))
+    nbytes = sum(_bytes(int(o), int(n)) for o, n in zip(ops, ns))
+    for prec in ("f64", "mixed_f32"):
+        ts = []
+        for rep in range(4):
+            rb.buf.copy_(pristine)
+            torch.cuda.synchronize()
+            e0, e1 = _events(torch)
+            e0.record()
+            tla.ragged(h, rb, prec)          # first call captures the graph, later ones replay it
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        t = float(np.median(ts[1:]))
+        idx = np.linspace(0, batch - 1, 48).astype(int)
+        worst = 0.0
+        for b in idx:
+            X = rb.result(b)
+            m = mats[b]
+            if ops[b] == 0:
+                e = oracle.eta_potrf(m[0], np.triu(X))
+            elif ops[b] == 1:
+                e = oracle.eta_trsyl(*m, X)
+            else:
+                e = oracle.eta_trlyap(*m, X)
+            worst = max(worst, e)
+        print(json.dumps({"workload": f"ragged {batch} (40/30/30 potrf/trsyl/trlyap, n~U{{3..128}}) prec={prec}",
+                          "solves_per_s": batch / t, "gflops_nominal": flops / t / 1e9, "gbs": nbytes / t / 1e9,
+                          "ms": t * 1e3, "first_call_ms_incl_capture": ts[0] * 1e3,
+                          "eta_max_sample": worst,
+                          "info_nonzero": int((rb.info.cpu().numpy() != 0).sum())}), flush=True)
+    sub = [mats[b] for b in range(512)]
+    t0 = time.perf_counter()
+    for b, m in enumerate(sub):
+        if ops[b] == 0:
+            oracle.potrf(m[0])
+        elif ops[b] == 1:
+            oracle.trsyl(*m)
+        else:
+            oracle.trlyap(*m)
+    tc = time.perf_counter() - t0
+    print(json.dumps({"workload": "ragged cpu oracle sample", "instances": 512, "solves_per_s": 512 / tc,
+                      "threads": 1}))
+
+
+def large(a):
+    import torch
+    import oracle
+    import paper_1906_08613_amd as tla
+    from paper_1906_08613_amd import inputs as I
+    h = tla.Handle(0)
+    batch = 256
+    for n in (256, 512, 1024):
+        for opname, op in (("potrf", 0), ("trsyl", 1), ("trlyap", 2)):
+            if op == 0:
+                A = I.potrf_problem("cfg4", n, batch)
+                d = [tla.to_device_cm(np.triu(A))]
+                o = tla.Operands(n, *d)
+                run = lambda: h.potrf_batched("f64", batch, n, o.n, o.ptrs[0], o.lds[0], o.info)
+            elif op == 1:
+                L, U, C = I.trsyl_problem("cfg4", n, batch)
+                d = [tla.to_device_cm(L), tla.to_device_cm(U), tla.to_device_cm(C)]
+                o = tla.Operands(n, *d)
+                run = lambda: h.trsyl_batched("f64", batch, n, o.n, o.ptrs[0], o.lds[0], o.ptrs[1], o.lds[1],
+                                              o.ptrs[2], o.lds[2], o.info)
+            else:
+                L, S = I.trlyap_problem("cfg4", n, batch)
+                d = [tla.to_device_cm(L), tla.to_device_cm(np.tril(S))]
+                o = tla.Operands(n, *d)
+                run = lambda: h.trlyap_batched("f64", batch, n, o.n, o.ptrs[0], o.lds[0], o.ptrs[1], o.lds[1],
+                                               o.info)
+            work = d[-1]
+            pristine = work.clone()
+            ts = []
+            for _ in range(2):
+                work.copy_(pristine)
+                torch.cuda.synchronize()
+                e0, e1 = _events(torch)
+                e0.record()
+                run()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+            t = min(ts)
+            X = tla.from_device_cm(work[:1])
+            if op == 0:
+                eta = oracle.eta_potrf_batch(A[:1], np.triu(X))
+            elif op == 1:
+                eta = oracle.eta_trsyl_batch(L[:1], U[:1], C[:1], X)
+            else:
+                eta = oracle.eta_trlyap_batch(L[:1], S[:1], X)
+            print(json.dumps({"workload": f"{opname} f64 n={n} x{batch}", "solves_per_s": batch / t,
+                              "gflops": batch * _flops(op, n) / t / 1e9,
+                              "frac_fp64_peak": batch * _flops(op, n) / t / 78.6e12,
+                              "ms": t * 1e3, "eta_sample": float(eta.max())}), flush=True)
+            del d, o, work, pristine
+            torch.cuda.empty_cache()
+
+
+def planner(a):
+    import os
+    import tempfile
+    import paper_1906_08613_amd as tla
+    h = tla.Handle(0)
+    ns = list(range(3, 129, 5))
+    t0 = time.perf_counter()
+    h.tune(["potrf", "trsyl", "trlyap"], ns, ["f64", "mixed_f32"], batch=1024, reps=2)
+    t_tune = time.perf_counter() - t0
+    path = os.path.join(tempfile.mkdtemp(), "table.txt")
+    h.save_table(path)
+    rec = np.loadtxt(path, comments="#")
+    times = {}
+    for r in rec:
+        times[(int(r[0]), int(r[1]), int(r[2]), tuple(int(x) for x in r[4:9]))] = r[9]
+    held = [n for n in ns if n % 7 == 0]
+    t0 = time.perf_counter()
+    hm = tla.Handle(0)
+    hm.load_table(path)
+    loss = hm.mlp_train(epochs=3000, lr=3e-3, seed=5, exclude_mod=7)
+    t_train = time.perf_counter() - t0
+    hu = tla.Handle(0)
+    hu.load_table(path)
+    hu.mlp_train(epochs=0, lr=3e-3, seed=5, exclude_mod=7)
+
+    def regret(handle, mode):
+        handle.set_picker(mode)
+        out = []
+        for op in range(3):
+            for prec in (0, 1):
+                for n in held:
+                    cand = {k[3]: v for k, v in times.items() if k[0] == op and k[1] == n and k[2] == prec}
+                    best = min(cand.values())
+                    pick = handle.get_plan(op, n, prec, 1024).astuple()
+                    out.append(cand.get(tuple(pick), np.inf) / best - 1.0)
+        return np.array(out)
+
+    r_mlp, r_untrained, r_default = regret(hm, tla.PICK_MLP), regret(hu, tla.PICK_MLP), regret(hu, tla.PICK_DEFAULT)
+    print(json.dumps({"workload": "planner: autotuner n=3..128 step 5, f64 + mixed_f32, batch 1024; MLP trained "
+                                  "without n % 7 == 0", "held_out_n": held, "records": len(times),
+                      "tune_seconds": t_tune, "train_seconds": t_train, "train_loss": loss,
+                      "regret_mlp_mean": float(r_mlp.mean()), "regret_mlp_max": float(r_mlp.max()),
+                      "regret_untrained_mean": float(r_untrained.mean()),
+                      "regret_default_plan_mean": float(r_default.mean())}))
+
+
+def run(a):
+    {"potrf16": potrf16, "sweep": sweep, "ragged": ragged, "large": large, "planner": planner}[a.workload](a)
