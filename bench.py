@@ -47,7 +47,9 @@ def parse():
     p.add_argument("--workload", default="headline",
                    choices=["headline", "potrf16", "sweep", "ragged", "large", "planner"],
                    help="headline: the metric's configuration (default); the others print their own lines")
-    p.add_argument("--tune", action="store_true", help="autotune the headline configuration first")
+    p.add_argument("--no-tune", action="store_true", help="skip autotuning the headline configuration first")
+    p.add_argument("--table", default=None, help="load a tuning table instead of tuning")
+    p.add_argument("--save-table", default=None, help="write the tuning table here")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     return p.parse_args()
@@ -258,8 +260,13 @@ def main():
     h = tla.Handle(0)
     n, batch = a.n, a.batch
     ops = a.ops.split(",")
-    if a.tune:
+    # plans: the autotuner's choice for this configuration (outside the timed region)
+    if a.table:
+        h.load_table(a.table)
+    elif not a.no_tune:
         h.tune(ops, [n], ["f64", a.prec], batch=batch, reps=3)
+    if a.save_table:
+        h.save_table(a.save_table)
     copies = max(a.steps, a.warmup)
     hosts = [(op, make_inputs(op, n, batch, a.kappa)) for op in ops]
     benches = [OpBench(tla, torch, h, op, host, copies, a.prec) for op, host in hosts]

@@ -66,14 +66,17 @@ TLA_DI double ingest(T* Wg, int ldw, int np, const double* Gg, int ldg, int n, i
   double ss = 0.0;
   for (int i0 = 0; i0 < np; i0 += 64) {
     const int i = i0 + l;
-    const int ic = i < n ? i : n - 1;
     for (int jb = w; jb < np; jb += NW * U) {
       double v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        // unconditional load from a clamped (always valid) address, then select
+        // unconditional load from a clamped address inside the kept part of
+        // the column (so no cache line outside it is fetched), then select
         const int j = jb + u * NW;
         const int jc = j < n ? j : n - 1;
+        int ic = i < n ? i : n - 1;
+        if (part < 0) ic = ic > jc ? ic : jc;
+        if (part > 0) ic = ic < jc ? ic : jc;
         const double raw = G[ic + (size_t)jc * ldg];
         const bool keep = i < n && j < n && (part == 0 || (part < 0 ? i >= j : i <= j));
         v[u] = keep ? raw : 0.0;
