@@ -124,14 +124,20 @@ TLA_DI void egress(double* Gg, int ldg, int n, const T* Wg, int ldw, int part) {
   }
 }
 
-// first zero denominator d_ij = a_i + b_j (column-major index + 1) into *info
+// first zero denominator d_ij = a_i + b_j (column-major index + 1) into *info:
+// each thread keeps its own minimum and publishes it once, so the loads of
+// the loop carry no dependence on the atomic
 template <class VA, class VB, class IP>
 TLA_DI void scan_zero_denoms(const VA& A, const VB& B, int n, bool lower_only, IP info) {
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int j = e / n, i = e - j * n;
-    if (lower_only && i < j) continue;
-    if (A(i, i) + B(j, j) == 0.0) atomicMin(info, 1 + e);
+  int best = INT_MAX;
+  const int nw = blockDim.x >> 6;
+  for (int j = wave_id(); j < n; j += nw) {
+    const auto bj = B(j, j);
+    for (int i = lower_only ? j + lane_id() : lane_id(); i < n; i += 64) {
+      if (A(i, i) + bj == 0.0) best = min(best, 1 + i + j * n);
+    }
   }
+  if (best != INT_MAX) atomicMin(info, best);
 }
 
 // One instance's operands and result slots (see KArgs for the roles).

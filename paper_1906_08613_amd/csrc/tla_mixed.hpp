@@ -111,13 +111,15 @@ TLA_DI MixedLds carve(unsigned char* smem, const KArgs& g, int naux) {
 
 // float view of an FP64 global matrix (coefficients read through the caches)
 template <class T>
-TLA_DI bool all_finite_lds(const T* W, int ldw, int n) {
+TLA_DI bool all_finite_lds(const T* Wg, int ldw, int n) {
+  const lds_t<T>* W = to_lds(const_cast<T*>(Wg));
   bool ok = true;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int j = e / n, i = e - j * n;
-    const T v = W[i + j * ldw];
-    ok = ok && (v - v == T(0));
-  }
+  const int nw = blockDim.x >> 6;
+  for (int j = wave_id(); j < n; j += nw)
+    for (int i = lane_id(); i < n; i += 64) {
+      const T v = W[i + j * ldw];
+      ok = ok && (v - v == T(0));
+    }
   return ok;
 }
 
@@ -145,12 +147,12 @@ TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
     sl = ingest<float, NW>(m.A1, ld, np, Lg, ldl, n, -1, 0.0f);
     su = ingest<float, NW>(m.A2, ld, np, Ug, ldu, n, +1, 0.0f);
   } else {
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const int j = e / n, i = e - j * n;
-      const double lv = L64(i, j), uv = U64(i, j);
-      sl += lv * lv;
-      su += uv * uv;
-    }
+    for (int j = wave_id(); j < n; j += NW)
+      for (int i = lane_id(); i < n; i += 64) {
+        const double lv = L64(i, j), uv = U64(i, j);
+        sl += lv * lv;
+        su += uv * uv;
+      }
   }
   const double nc = sqrt(block_sum<NW>(sc, m.red));
   const double nl = sqrt(block_sum<NW>(sl, m.red));
@@ -159,9 +161,10 @@ TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
   // exact zero denominators (FP64) decide info; FP32 ones only force the FP64 path
   scan_zero_denoms(L64, U64, n, false, m.info);
   int lo_zero = 0;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int j = e / n, i = e - j * n;
-    if (float(L64(i, i)) + float(U64(j, j)) == 0.0f) lo_zero = TLA_STAT_BREAKDOWN;
+  for (int j = wave_id(); j < n; j += NW) {
+    const float uj = float(U64(j, j));
+    for (int i = lane_id(); i < n; i += 64)
+      if (float(L64(i, i)) + uj == 0.0f) lo_zero = TLA_STAT_BREAKDOWN;
   }
   bad |= block_or<NW>(lo_zero | bad, m.ired);
   st.flags |= bad;
@@ -185,8 +188,9 @@ TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
           Tile<double, TB> c, x;
           tload(c, C64.sub(I * TB, J * TB));
           tload(x, Xv.sub(I * TB, J * TB));
-          for (int K = 0; K <= I; ++K) Gemm<double, TB, E64>::sub(c, L64.sub(I * TB, K * TB), Xv.sub(K * TB, J * TB));
-          for (int K = 0; K <= J; ++K) Gemm<double, TB, E64>::sub(c, Xv.sub(I * TB, K * TB), U64.sub(K * TB, J * TB));
+          typedef Gemm<double, TB, E64> G64;
+          gemm_sum<G64>(c, 0, I + 1, [&](int K) { return L64.sub(I * TB, K * TB); }, [&](int K) { return Xv.sub(K * TB, J * TB); });
+          gemm_sum<G64>(c, 0, J + 1, [&](int K) { return Xv.sub(I * TB, K * TB); }, [&](int K) { return U64.sub(K * TB, J * TB); });
           const int l = lane_id(), j = tcol<TB>(l);
 #pragma unroll
           for (int r = 0; r < Tile<double, TB>::EPL; ++r) {
@@ -253,11 +257,11 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
   if constexpr (LU_LDS) {
     sl = ingest<float, NW>(m.A1, ld, np, Lg, ldl, n, -1, 0.0f);
   } else {
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const int j = e / n, i = e - j * n;
-      const double lv = L64(i, j);
-      sl += lv * lv;
-    }
+    for (int j = wave_id(); j < n; j += NW)
+      for (int i = lane_id(); i < n; i += 64) {
+        const double lv = L64(i, j);
+        sl += lv * lv;
+      }
   }
   __syncthreads();
   mirror_lower(m.W, ld, np);
@@ -266,9 +270,10 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
   int bad = (ns - ns != 0.0 || nl - nl != 0.0) ? TLA_STAT_NONFINITE : 0;
   scan_zero_denoms(L64, L64, n, true, m.info);
   int lo_zero = 0;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int j = e / n, i = e - j * n;
-    if (i >= j && float(L64(i, i)) + float(L64(j, j)) == 0.0f) lo_zero = TLA_STAT_BREAKDOWN;
+  for (int j = wave_id(); j < n; j += NW) {
+    const float lj = float(L64(j, j));
+    for (int i = j + lane_id(); i < n; i += 64)
+      if (float(L64(i, i)) + lj == 0.0f) lo_zero = TLA_STAT_BREAKDOWN;
   }
   bad |= block_or<NW>(lo_zero | bad, m.ired);
   st.flags |= bad;
@@ -294,8 +299,9 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
           Tile<double, TB> c, x;
           tload(c, S64.sub(I * TB, J * TB));
           tload(x, Xv.sub(I * TB, J * TB));
-          for (int K = 0; K <= I; ++K) Gemm<double, TB, E64>::sub(c, L64.sub(I * TB, K * TB), Xv.sub(K * TB, J * TB));
-          for (int K = 0; K <= J; ++K) Gemm<double, TB, E64>::sub(c, Xv.sub(I * TB, K * TB), L64.sub(J * TB, K * TB).t());
+          typedef Gemm<double, TB, E64> G64;
+          gemm_sum<G64>(c, 0, I + 1, [&](int K) { return L64.sub(I * TB, K * TB); }, [&](int K) { return Xv.sub(K * TB, J * TB); });
+          gemm_sum<G64>(c, 0, J + 1, [&](int K) { return Xv.sub(I * TB, K * TB); }, [&](int K) { return L64.sub(J * TB, K * TB).t(); });
           const double wgt = I == J ? 1.0 : 2.0;
           const int l = lane_id(), j = tcol<TB>(l);
 #pragma unroll
@@ -361,7 +367,7 @@ TLA_DI void newton_correction(const VW& Wv, const VW& Xv, const VXd& Xd, int nt,
     for (int I = 0; I < nt; ++I) {
       Tile<T, TB> c;
       tload(c, Wv.sub(I * TB, J * TB));
-      for (int K = 0; K < I; ++K) G::sub(c, Xv.sub(K * TB, I * TB).t(), Wv.sub(K * TB, J * TB));
+      gemm_sum<G>(c, 0, I, [&](int K) { return Xv.sub(K * TB, I * TB).t(); }, [&](int K) { return Wv.sub(K * TB, J * TB); });
       tile_trsm_ut<T, TB>(c, Xv.sub(I * TB, I * TB), wbuf);
       tstore(c, Wv.sub(I * TB, J * TB));
     }
@@ -371,7 +377,7 @@ TLA_DI void newton_correction(const VW& Wv, const VW& Xv, const VXd& Xd, int nt,
     for (int J = 0; J < nt; ++J) {
       Tile<T, TB> c;
       tload(c, Wv.sub(I * TB, J * TB));
-      for (int K = 0; K < J; ++K) G::sub(c, Wv.sub(I * TB, K * TB), Xv.sub(K * TB, J * TB));
+      gemm_sum<G>(c, 0, J, [&](int K) { return Wv.sub(I * TB, K * TB); }, [&](int K) { return Xv.sub(K * TB, J * TB); });
       tile_trsm_right_u<T, TB>(c, Xv.sub(J * TB, J * TB), wbuf);
       tstore(c, Wv.sub(I * TB, J * TB));
     }
@@ -391,7 +397,7 @@ TLA_DI void newton_correction(const VW& Wv, const VW& Xv, const VXd& Xd, int nt,
     if (I > J) continue;
     Tile<T, TB> c;
     tzero(c);
-    for (int K = I; K <= J; ++K) G::sub(c, Wv.sub(I * TB, K * TB), Xv.sub(K * TB, J * TB));
+    gemm_sum<G>(c, I, J + 1, [&](int K) { return Wv.sub(I * TB, K * TB); }, [&](int K) { return Xv.sub(K * TB, J * TB); });
     const int l = lane_id(), j = tcol<TB>(l);
 #pragma unroll
     for (int r = 0; r < Tile<T, TB>::EPL; ++r) {
@@ -438,7 +444,7 @@ TLA_DI void potrf_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
         if (I > J) continue;
         Tile<double, TB> c;
         tload(c, A64.sub(I * TB, J * TB));
-        for (int K = 0; K <= I; ++K) Gemm<double, TB, E64>::sub(c, Xv.sub(K * TB, I * TB).t(), Xv.sub(K * TB, J * TB));
+        gemm_sum<Gemm<double, TB, E64>>(c, 0, I + 1, [&](int K) { return Xv.sub(K * TB, I * TB).t(); }, [&](int K) { return Xv.sub(K * TB, J * TB); });
         const double wgt = I == J ? 1.0 : 2.0;
         const int l = lane_id(), j = tcol<TB>(l);
 #pragma unroll

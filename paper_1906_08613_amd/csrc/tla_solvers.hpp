@@ -80,7 +80,7 @@ TLA_DI void potrf_blocked(const VA& A, const Ctx<T>& cx) {
       for (int J = K + w; J < nt; J += NW) {
         Tile<T, TB> c;
         tload(c, A.sub(K * TB, J * TB));
-        for (int P = 0; P < K; ++P) G::sub(c, A.sub(P * TB, K * TB).t(), A.sub(P * TB, J * TB));
+        gemm_sum<G>(c, 0, K, [&](int P) { return A.sub(P * TB, K * TB).t(); }, [&](int P) { return A.sub(P * TB, J * TB); });
         if (J == K) tile_potf2<T, TB>(c, cx.wbuf, cx.n - K * TB, K * TB, cx.info);
         tstore(c, A.sub(K * TB, J * TB));
       }
@@ -102,13 +102,13 @@ TLA_DI void potrf_blocked(const VA& A, const Ctx<T>& cx) {
         for (int I = 0; I < K; ++I) {
           Tile<T, TB> c;
           tload(c, A.sub(I * TB, K * TB));
-          for (int P = 0; P < I; ++P) G::sub(c, A.sub(P * TB, I * TB).t(), A.sub(P * TB, K * TB));
+          gemm_sum<G>(c, 0, I, [&](int P) { return A.sub(P * TB, I * TB).t(); }, [&](int P) { return A.sub(P * TB, K * TB); });
           tile_trsm_ut<T, TB>(c, A.sub(I * TB, I * TB), cx.wbuf);
           tstore(c, A.sub(I * TB, K * TB));
         }
         Tile<T, TB> c;
         tload(c, A.sub(K * TB, K * TB));
-        for (int P = 0; P < K; ++P) G::sub(c, A.sub(P * TB, K * TB).t(), A.sub(P * TB, K * TB));
+        gemm_sum<G>(c, 0, K, [&](int P) { return A.sub(P * TB, K * TB).t(); }, [&](int P) { return A.sub(P * TB, K * TB); });
         tile_potf2<T, TB>(c, cx.wbuf, cx.n - K * TB, K * TB, cx.info);
         tstore(c, A.sub(K * TB, K * TB));
       }
@@ -143,8 +143,8 @@ TLA_DI void trsyl_blocked(const VX& X, const VL& L, const VU& U, const Ctx<T>& c
         const int J = d - I;
         Tile<T, TB> c;
         tload(c, X.sub(I * TB, J * TB));
-        for (int K = 0; K < I; ++K) G::sub(c, L.sub(I * TB, K * TB), X.sub(K * TB, J * TB));
-        for (int K = 0; K < J; ++K) G::sub(c, X.sub(I * TB, K * TB), U.sub(K * TB, J * TB));
+        gemm_sum<G>(c, 0, I, [&](int K) { return L.sub(I * TB, K * TB); }, [&](int K) { return X.sub(K * TB, J * TB); });
+        gemm_sum<G>(c, 0, J, [&](int K) { return X.sub(I * TB, K * TB); }, [&](int K) { return U.sub(K * TB, J * TB); });
         syl_tile_solve<T, TB>(c, L, U, cx, I, J);
         tstore(c, X.sub(I * TB, J * TB));
       }
@@ -156,7 +156,7 @@ TLA_DI void trsyl_blocked(const VX& X, const VL& L, const VU& U, const Ctx<T>& c
         for (int J = w; J < nt; J += NW) {
           Tile<T, TB> c;
           tload(c, X.sub(I * TB, J * TB));
-          for (int K = 0; K < I; ++K) G::sub(c, L.sub(I * TB, K * TB), X.sub(K * TB, J * TB));
+          gemm_sum<G>(c, 0, I, [&](int K) { return L.sub(I * TB, K * TB); }, [&](int K) { return X.sub(K * TB, J * TB); });
           tstore(c, X.sub(I * TB, J * TB));
         }
         __syncthreads();
@@ -165,7 +165,7 @@ TLA_DI void trsyl_blocked(const VX& X, const VL& L, const VU& U, const Ctx<T>& c
         for (int J = 0; J < nt; ++J) {
           Tile<T, TB> c;
           tload(c, X.sub(I * TB, J * TB));
-          for (int K = 0; K < J; ++K) G::sub(c, X.sub(I * TB, K * TB), U.sub(K * TB, J * TB));
+          gemm_sum<G>(c, 0, J, [&](int K) { return X.sub(I * TB, K * TB); }, [&](int K) { return U.sub(K * TB, J * TB); });
           syl_tile_solve<T, TB>(c, L, U, cx, I, J);
           tstore(c, X.sub(I * TB, J * TB));
         }
@@ -189,7 +189,7 @@ TLA_DI void trsyl_blocked(const VX& X, const VL& L, const VU& U, const Ctx<T>& c
         for (int I = w; I < nt; I += NW) {
           Tile<T, TB> c;
           tload(c, X.sub(I * TB, J * TB));
-          for (int K = 0; K < J; ++K) G::sub(c, X.sub(I * TB, K * TB), U.sub(K * TB, J * TB));
+          gemm_sum<G>(c, 0, J, [&](int K) { return X.sub(I * TB, K * TB); }, [&](int K) { return U.sub(K * TB, J * TB); });
           tstore(c, X.sub(I * TB, J * TB));
         }
         __syncthreads();
@@ -198,7 +198,7 @@ TLA_DI void trsyl_blocked(const VX& X, const VL& L, const VU& U, const Ctx<T>& c
         for (int I = 0; I < nt; ++I) {
           Tile<T, TB> c;
           tload(c, X.sub(I * TB, J * TB));
-          for (int K = 0; K < I; ++K) G::sub(c, L.sub(I * TB, K * TB), X.sub(K * TB, J * TB));
+          gemm_sum<G>(c, 0, I, [&](int K) { return L.sub(I * TB, K * TB); }, [&](int K) { return X.sub(K * TB, J * TB); });
           syl_tile_solve<T, TB>(c, L, U, cx, I, J);
           tstore(c, X.sub(I * TB, J * TB));
         }
@@ -256,16 +256,14 @@ TLA_DI void lya_tile_solve(Tile<T, TB>& c, const VX& X, const VL& L, const Ctx<T
 template <class T, int TB, int ENG, class VX, class VL>
 TLA_DI void lya_colside(Tile<T, TB>& c, const VX& X, const VL& L, int I, int J, int k0, int k1) {
   typedef Gemm<T, TB, ENG> G;
-  for (int K = k0; K < k1; ++K) {
-    if (K >= J) G::sub(c, L.sub(I * TB, K * TB), X.sub(K * TB, J * TB));
-    else G::sub(c, L.sub(I * TB, K * TB), X.sub(J * TB, K * TB).t());
-  }
+  gemm_sum<G>(c, k0, k1, [&](int K) { return L.sub(I * TB, K * TB); },
+              [&](int K) { return K >= J ? X.sub(K * TB, J * TB) : X.sub(J * TB, K * TB).t(); });
 }
 // row-side lazy update: c -= sum_{K in [k0,k1)} X_IK L_JK^T
 template <class T, int TB, int ENG, class VX, class VL>
 TLA_DI void lya_rowside(Tile<T, TB>& c, const VX& X, const VL& L, int I, int J, int k0, int k1) {
   typedef Gemm<T, TB, ENG> G;
-  for (int K = k0; K < k1; ++K) G::sub(c, X.sub(I * TB, K * TB), L.sub(J * TB, K * TB).t());
+  gemm_sum<G>(c, k0, k1, [&](int K) { return X.sub(I * TB, K * TB); }, [&](int K) { return L.sub(J * TB, K * TB).t(); });
 }
 
 template <class T, int TB, int ENG, int NW, int VAR, class VX, class VL>
@@ -317,7 +315,7 @@ TLA_DI void trlyap_blocked(const VX& X, const VL& L, const Ctx<T>& cx) {
         // tiles below: L_II X_IK + X_IK L_KK^T = S_IK - L_IK X_KK - sum_{K<P<I} L_IP X_PK
         for (int I = K + 1; I < nt; ++I) {
           tload(c, X.sub(I * TB, K * TB));
-          for (int P = K; P < I; ++P) G::sub(c, L.sub(I * TB, P * TB), X.sub(P * TB, K * TB));
+          gemm_sum<G>(c, K, I, [&](int P) { return L.sub(I * TB, P * TB); }, [&](int P) { return X.sub(P * TB, K * TB); });
           lya_tile_solve<T, TB>(c, X, L, cx, I, K);
         }
       }

@@ -144,15 +144,30 @@ template <class T, int TB, int ENG>
 struct Gemm;
 
 // Matrix cores in the working precision (f64 16x16x4 or f32 16x16x4).
+// load() fetches one step's operand fragments, mma() consumes them.
 template <class T>
 struct Gemm<T, 16, ENG_MFMA> {
+  struct F { T a[4], b[4]; };
   template <class VA, class VB>
-  static TLA_DI void sub(Tile<T, 16>& c, const VA& A, const VB& B) {
+  static TLA_DI void load(F& f, const VA& A, const VB& B) {
     const int l = lane_id(), i = l & 15, kq = l >> 4;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      f.a[kk] = -A(i, 4 * kk + kq);
+      f.b[kk] = B(4 * kk + kq, i);
+    }
+  }
+  static TLA_DI void mma(Tile<T, 16>& c, const F& f) {
     typename Frag<T>::acc acc = {c.v[0], c.v[1], c.v[2], c.v[3]};
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = Frag<T>::mma(-A(i, 4 * kk + kq), B(4 * kk + kq, i), acc);
+    for (int kk = 0; kk < 4; ++kk) acc = Frag<T>::mma(f.a[kk], f.b[kk], acc);
     c.v[0] = acc[0]; c.v[1] = acc[1]; c.v[2] = acc[2]; c.v[3] = acc[3];
+  }
+  template <class VA, class VB>
+  static TLA_DI void sub(Tile<T, 16>& c, const VA& A, const VB& B) {
+    F f;
+    load(f, A, B);
+    mma(c, f);
   }
 };
 
@@ -160,34 +175,50 @@ struct Gemm<T, 16, ENG_MFMA> {
 // only): the operands are rounded to the 16-bit type, K = 16 in one step.
 template <>
 struct Gemm<float, 16, ENG_MFMA_F16> {
+  struct F { h4 a, b; };
   template <class VA, class VB>
-  static TLA_DI void sub(Tile<float, 16>& c, const VA& A, const VB& B) {
+  static TLA_DI void load(F& f, const VA& A, const VB& B) {
     const int l = lane_id(), i = l & 15, kq = l >> 4;
-    h4 a, b;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      a[e] = (_Float16)(-A(i, 4 * kq + e));
-      b[e] = (_Float16)(B(4 * kq + e, i));
+      f.a[e] = (_Float16)(-A(i, 4 * kq + e));
+      f.b[e] = (_Float16)(B(4 * kq + e, i));
     }
+  }
+  static TLA_DI void mma(Tile<float, 16>& c, const F& f) {
     f4 acc = {c.v[0], c.v[1], c.v[2], c.v[3]};
-    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(f.a, f.b, acc, 0, 0, 0);
     c.v[0] = acc[0]; c.v[1] = acc[1]; c.v[2] = acc[2]; c.v[3] = acc[3];
+  }
+  template <class VA, class VB>
+  static TLA_DI void sub(Tile<float, 16>& c, const VA& A, const VB& B) {
+    F f;
+    load(f, A, B);
+    mma(c, f);
   }
 };
 template <>
 struct Gemm<float, 16, ENG_MFMA_BF16> {
+  struct F { s4 a, b; };
   template <class VA, class VB>
-  static TLA_DI void sub(Tile<float, 16>& c, const VA& A, const VB& B) {
+  static TLA_DI void load(F& f, const VA& A, const VB& B) {
     const int l = lane_id(), i = l & 15, kq = l >> 4;
-    s4 a, b;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      a[e] = __builtin_bit_cast(short, (__bf16)(-A(i, 4 * kq + e)));
-      b[e] = __builtin_bit_cast(short, (__bf16)(B(4 * kq + e, i)));
+      f.a[e] = __builtin_bit_cast(short, (__bf16)(-A(i, 4 * kq + e)));
+      f.b[e] = __builtin_bit_cast(short, (__bf16)(B(4 * kq + e, i)));
     }
+  }
+  static TLA_DI void mma(Tile<float, 16>& c, const F& f) {
     f4 acc = {c.v[0], c.v[1], c.v[2], c.v[3]};
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f.a, f.b, acc, 0, 0, 0);
     c.v[0] = acc[0]; c.v[1] = acc[1]; c.v[2] = acc[2]; c.v[3] = acc[3];
+  }
+  template <class VA, class VB>
+  static TLA_DI void sub(Tile<float, 16>& c, const VA& A, const VB& B) {
+    F f;
+    load(f, A, B);
+    mma(c, f);
   }
 };
 
@@ -205,6 +236,15 @@ struct Gemm<T, TB, ENG_VALU> {
     }
   }
 };
+
+// c -= sum_{K = k0}^{k1 - 1} fa(K) * fb(K), where fa / fb return the operand
+// views of step K.  (Fetching step K + 1's fragments ahead of step K's
+// products was measured slower: it raised register use and lowered the
+// number of resident waves.)
+template <class G, class Tl, class FA, class FB>
+TLA_DI void gemm_sum(Tl& c, int k0, int k1, const FA& fa, const FB& fb) {
+  for (int K = k0; K < k1; ++K) G::sub(c, fa(K), fb(K));
+}
 
 // ------------------------------------------------------ tile solvers
 // All solvers run on one wavefront; `buf` is that wave's private LDS scratch
@@ -256,7 +296,7 @@ TLA_DI void tile_sylv(Tile<T, TB>& c, const VL& Lt, const VU& Ut, lds_t<T>* buf,
       rowbuf[0] = x;
     }
   }
-#pragma unroll 2
+#pragma unroll 1
   for (int s = 0; s < 2 * TB - 1; ++s) {
     int k = s - j;
     k = k < 0 ? 0 : (k > TB - 1 ? TB - 1 : k);
