@@ -248,23 +248,32 @@ TLA_DI void gemm_sum(Tl& c, int k0, int k1, const FA& fa, const FB& fb) {
 
 // ------------------------------------------------------ tile solvers
 // All solvers run on one wavefront; `buf` is that wave's private LDS scratch
-// of at least 3*TB elements.
-
-// Triangular Sylvester on one tile:  Lt X + X Ut = c  (Lt lower, Ut upper,
-// TB x TB views), overwriting c with X.  Element (i, j) is final once every
-// (k, j), k < i and (i, k), k < j is; all elements on the anti-diagonal
-// i + j = s are finalised together and then subtract their contribution
-// from the elements below them in their column and right of them in their
-// row.  Elements with i >= ni or j >= nj (padding) are forced to zero.
+// of wave_scratch(TB) elements.
 //
-// The strictly triangular parts of Lt and Ut are first staged in the wave's
-// scratch and the broadcast vectors are zeroed, so that the update of every
-// step needs no test: a coefficient outside the strict triangle is zero, and
-// a broadcast value not yet produced is zero.  One LDS fence per
-// anti-diagonal: values finalised for step s + 1 are published at the end of
-// step s, after this step's reads (the LDS serves a wave in order).
+// The 16 x 16 solvers first move the tile out of the matrix-core layout into
+// one where every lane owns a small contiguous piece: a 2 x 2 block for the
+// Sylvester tile, a strip of 4 consecutive elements of one column (or row) for
+// the triangular solves and the Cholesky factorisation.  Most of the dependent
+// chain then runs inside a lane's registers and the lanes exchange values once
+// per block step (15 block anti-diagonals, or 4 strips) instead of once per
+// element step (31 anti-diagonals, or 16 rows); the tile goes back to the
+// matrix-core layout at the end.  The 8 x 8 tiles (one element per lane) use
+// element-wise schedules.
+
+// ---- Sylvester tile:  Lt X + X Ut = c  (Lt lower, Ut upper), c := X.
+// Element (i, j) depends on the elements above it in its column and left of
+// it in its row; everything with i >= ni or j >= nj is padding, forced to 0.
+
+// Element schedule (any TB): the anti-diagonal i + j = s is finalised at step
+// s - 1 and subtracts its contribution from the elements below it in its
+// column and right of it in its row.  The strict triangles of Lt and Ut are
+// staged in the scratch and the broadcast vectors start at zero, so the
+// update of every step needs no test: a coefficient outside the strict
+// triangle is zero and a value not yet produced is zero.  One LDS fence per
+// step: values finalised for step s + 1 are published at the end of step s,
+// after this step's reads (the LDS serves a wave in order).
 template <class T, int TB, class VL, class VU>
-TLA_DI void tile_sylv(Tile<T, TB>& c, const VL& Lt, const VU& Ut, lds_t<T>* buf, int ni, int nj) {
+TLA_DI void tile_sylv_elem(Tile<T, TB>& c, const VL& Lt, const VU& Ut, lds_t<T>* buf, int ni, int nj) {
   const int l = lane_id(), j = tcol<TB>(l);
   constexpr int E = Tile<T, TB>::EPL;
   constexpr int LD = TB + 1;
@@ -331,14 +340,140 @@ TLA_DI void tile_sylv(Tile<T, TB>& c, const VL& Lt, const VU& Ut, lds_t<T>* buf,
   wave_fence();
 }
 
-// Upper Cholesky of a diagonal tile held in c (only j >= i is used/valid):
-// unblocked right-looking.  Pivots of rows >= nv are padding (value 1).
-// The first failing pivot (<= 0 or NaN) is reported as base + k + 1 into
-// *info if *info is still 0.  Row k of the partly updated tile is final
+// 2 x 2 block schedule (TB = 16): lane l owns block (I, J) = (l >> 3, l & 7),
+// elements (2I + a, 2J + b).  Block (I, J) obeys
+//   L_II X_IJ + X_IJ U_JJ = C_IJ - sum_{K<I} L_IK X_KJ - sum_{K<J} X_IK U_KJ,
+// a 2 x 2 Sylvester system solved in registers once the block anti-diagonal
+// I + J - 1 has been subtracted.  Step D subtracts the blocks of anti-diagonal
+// D (published in cb / rb) and finalises anti-diagonal D + 1.  Staged
+// coefficient blocks are zero outside the strict block triangles and the
+// broadcast blocks start at zero, as in the element schedule.
+template <int TB>
+TLA_DI int blk2_index(int i, int j) {  // element (i, j) of a tile stored as 2 x 2 blocks
+  return 4 * ((TB / 2) * (i >> 1) + (j >> 1)) + 2 * (i & 1) + (j & 1);
+}
+
+template <class T, class VL, class VU>
+TLA_DI void tile_sylv_blk2(Tile<T, 16>& c, const VL& Lt, const VU& Ut, lds_t<T>* buf, int ni, int nj) {
+  const int l = lane_id(), I = l >> 3, J = l & 7;
+  lds_t<T>* Lb = buf;        // block (I, K) at 4 (8 I + K): Lt's block if K < I, else 0
+  lds_t<T>* Ub = buf + 256;  // block (K, J) at 4 (8 K + J): Ut's block if K < J, else 0
+  lds_t<T>* cb = buf + 512;  // cb[J]: block of column J finalised at the last step
+  lds_t<T>* rb = buf + 544;  // rb[I]: block of row I finalised at the last step
+  {
+    const int lj = tcol<16>(l);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Lb[blk2_index<16>(trow<T, 16>(l, r), lj)] = c.v[r];
+  }
+  wave_fence();
+  T x[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) x[e] = Lb[4 * l + e];
+  // the reads above are served before these writes (same wave, LDS in order)
+  const int i0 = 2 * I, j0 = 2 * J;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const T lv = Lt(i0 + a, j0 + b), uv = Ut(i0 + a, j0 + b);
+      Lb[4 * l + 2 * a + b] = J < I ? lv : T(0);
+      Ub[4 * l + 2 * a + b] = I < J ? uv : T(0);
+    }
+  if (l < 8) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      cb[4 * l + e] = T(0);
+      rb[4 * l + e] = T(0);
+    }
+  }
+  const T l00 = Lt(i0, i0), l10 = Lt(i0 + 1, i0), l11 = Lt(i0 + 1, i0 + 1);
+  const T u00 = Ut(j0, j0), u01 = Ut(j0, j0 + 1), u11 = Ut(j0 + 1, j0 + 1);
+  const bool r0 = i0 < ni, r1 = i0 + 1 < ni, c0 = j0 < nj, c1 = j0 + 1 < nj;
+  const T q00 = (r0 && c0) ? T(1) / (l00 + u00) : T(0);
+  const T q01 = (r0 && c1) ? T(1) / (l00 + u11) : T(0);
+  const T q10 = (r1 && c0) ? T(1) / (l11 + u00) : T(0);
+  const T q11 = (r1 && c1) ? T(1) / (l11 + u11) : T(0);
+  // the 2 x 2 system by elements: (0,0), then (0,1) and (1,0), then (1,1)
+  auto finalise = [&]() {
+    const T y00 = x[0] * q00;
+    const T y01 = (x[1] - y00 * u01) * q01;
+    const T y10 = (x[2] - l10 * y00) * q10;
+    const T y11 = (x[3] - l10 * y01 - y10 * u01) * q11;
+    x[0] = y00; x[1] = y01; x[2] = y10; x[3] = y11;
+  };
+  wave_fence();
+  if (l == 0) {
+    finalise();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      cb[e] = x[e];
+      rb[e] = x[e];
+    }
+  }
+#pragma unroll 1
+  for (int D = 0; D < 14; ++D) {
+    int K = D - J, K2 = D - I;
+    K = (K >= 0 && K < 8) ? K : I;     // out of range: a zero block of Lb
+    K2 = (K2 >= 0 && K2 < 8) ? K2 : J;
+    T lk[4], uk[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      lk[e] = Lb[4 * (8 * I + K) + e];
+      uk[e] = Ub[4 * (8 * K2 + J) + e];
+    }
+    wave_fence();
+    T xc[4], xr[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      xc[e] = cb[4 * J + e];
+      xr[e] = rb[4 * I + e];
+    }
+    // c -= L_IK X_KJ + X_IK' U_K'J on row-major 2 x 2 blocks
+    x[0] -= lk[0] * xc[0] + lk[1] * xc[2] + xr[0] * uk[0] + xr[1] * uk[2];
+    x[1] -= lk[0] * xc[1] + lk[1] * xc[3] + xr[0] * uk[1] + xr[1] * uk[3];
+    x[2] -= lk[2] * xc[0] + lk[3] * xc[2] + xr[2] * uk[0] + xr[3] * uk[2];
+    x[3] -= lk[2] * xc[1] + lk[3] * xc[3] + xr[2] * uk[1] + xr[3] * uk[3];
+    if (I + J == D + 1) {
+      finalise();
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        cb[4 * J + e] = x[e];
+        rb[4 * I + e] = x[e];
+      }
+    }
+  }
+  wave_fence();
+  // back to the matrix-core layout (the loop's reads of Lb were served first)
+#pragma unroll
+  for (int e = 0; e < 4; ++e) Lb[4 * l + e] = x[e];
+  wave_fence();
+  {
+    const int lj = tcol<16>(l);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c.v[r] = Lb[blk2_index<16>(trow<T, 16>(l, r), lj)];
+  }
+  wave_fence();
+}
+
+template <class T, int TB, class VL, class VU>
+TLA_DI void tile_sylv(Tile<T, TB>& c, const VL& Lt, const VU& Ut, lds_t<T>* buf, int ni, int nj) {
+  if constexpr (TB == 16) tile_sylv_blk2<T>(c, Lt, Ut, buf, ni, nj);
+  else tile_sylv_elem<T, TB>(c, Lt, Ut, buf, ni, nj);
+}
+
+// ---- Upper Cholesky of a diagonal tile held in c (only j >= i is used and
+// written; the strict lower part is left as it is).  Pivots of rows >= nv are
+// padding (value 1).  The first failing pivot (<= 0 or NaN) is reported as
+// base + k + 1 into *info if *info is still 0.  The diagonal is sqrt(pivot)
+// and a row is scaled by the reciprocal of its diagonal, as in the element
+// recurrence.
+
+// Element schedule, right-looking: row k of the partly updated tile is final
 // after step k - 1; its owners publish it, and after one fence every lane
-// forms the pivot and the scaled row entries it needs itself.
+// reads the pivot and the row entries it needs (all reads of a step are
+// issued together) and forms the step's values itself.
 template <class T, int TB>
-TLA_DI void tile_potf2(Tile<T, TB>& c, lds_t<T>* buf, int nv, int base, lds_t<int>* info) {
+TLA_DI void tile_potf2_elem(Tile<T, TB>& c, lds_t<T>* buf, int nv, int base, lds_t<int>* info) {
   const int l = lane_id(), j = tcol<TB>(l);
   constexpr int E = Tile<T, TB>::EPL;
   lds_t<T>* rowk = buf;   // rowk[j] = a_kj after the updates of steps < k
@@ -349,37 +484,155 @@ TLA_DI void tile_potf2(Tile<T, TB>& c, lds_t<T>* buf, int nv, int base, lds_t<in
   for (int k = 0; k < TB; ++k) {
     wave_fence();
     const T p = rowk[k];
+    const T rj = rowk[j];
+    T ri[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) ri[r] = rowk[trow<T, TB>(l, r)];
+    const int inf0 = *info;
     const T d = sqrt(p);
     const T rd = T(1) / d;
-    const T xj = rowk[j] * rd;
-    if (l == 0 && !(p > T(0)) && k < nv && *info == 0) *info = base + k + 1;
+    const T xj = rj * rd;
+    if (l == 0 && !(p > T(0)) && k < nv && inf0 == 0) *info = base + k + 1;
+    T pub = T(0);
+    bool has = false;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int i = trow<T, TB>(l, r);
-      if (i == k) c.v[r] = (j == k) ? d : (j > k ? xj : c.v[r]);
-      else if (i > k && j >= i) c.v[r] -= (rowk[i] * rd) * xj;
+      const T upd = c.v[r] - (ri[r] * rd) * xj;
+      const T rowv = (j == k) ? d : (j > k ? xj : c.v[r]);
+      c.v[r] = (i == k) ? rowv : ((i > k && j >= i) ? upd : c.v[r]);
+      pub = (i == k + 1) ? c.v[r] : pub;
+      has = has || i == k + 1;
     }
-    // row k + 1 is now final: publish it (reads of rowk above came first)
-#pragma unroll
-    for (int r = 0; r < E; ++r)
-      if (trow<T, TB>(l, r) == k + 1) rowk[j] = c.v[r];
+    // row k + 1 is now final: publish it (this step's reads were issued first)
+    if (has) rowk[j] = pub;
   }
   wave_fence();
 }
 
-// Left solve with the transpose of an upper-triangular diagonal tile:
-// c := Xd^{-T} c  (forward substitution down every column).  Row k of the
-// solution is final after step k - 1 and is published then.
+// 4-row strip schedule (TB = 16): lane (g, j) = (l >> 4, l & 15) holds rows
+// 4g..4g+3 of column j.  Block step G: strip G has been updated by all
+// earlier strips and is published; every lane reads the 4 x 4 diagonal block
+// and factors it itself, solves its own column segment X_G,j = X_GG^{-T} A_G,j
+// and, below strip G, the segments of the columns that match its rows, then
+// subtracts X_G,i^T X_G,j from its strip.  Strip G + 1 publishes for the next
+// step.
+template <class T>
+TLA_DI void tile_potf2_strip(Tile<T, 16>& c, lds_t<T>* buf, int nv, int base, lds_t<int>* info) {
+  const int l = lane_id(), j = l & 15, g = l >> 4;
+  constexpr int LD = 17;
+  lds_t<T>* S = buf;  // the tile, column-major, leading dimension 17
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[trow<T, 16>(l, r) + j * LD] = c.v[r];
+  wave_fence();
+  T a[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) a[e] = S[4 * g + e + j * LD];
+  int bad = 0;
+#pragma unroll 1
+  for (int G = 0; G < 4; ++G) {
+    const int o = 4 * G;
+    T d[4][4], w[4], v[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+#pragma unroll
+      for (int q = p; q < 4; ++q) d[p][q] = S[o + p + (o + q) * LD];
+      w[p] = S[o + p + j * LD];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) v[e][p] = S[o + p + (4 * g + e) * LD];
+    // X_GG: upper Cholesky of the diagonal block, rr[p] = 1 / x_pp
+    T x[4][4], rr[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      T piv = d[p][p];
+#pragma unroll
+      for (int k = 0; k < p; ++k) piv -= x[k][p] * x[k][p];
+      if (!(piv > T(0)) && o + p < nv && bad == 0) bad = base + o + p + 1;
+      x[p][p] = sqrt(piv);
+      rr[p] = T(1) / x[p][p];
+#pragma unroll
+      for (int q = p + 1; q < 4; ++q) {
+        T s = d[p][q];
+#pragma unroll
+        for (int k = 0; k < p; ++k) s -= x[k][p] * x[k][q];
+        x[p][q] = s * rr[p];
+      }
+    }
+    // own column segment y = X_GG^{-T} A_G,j
+    T y[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      T s = w[p];
+#pragma unroll
+      for (int k = 0; k < p; ++k) s -= x[k][p] * y[k];
+      y[p] = s * rr[p];
+    }
+    if (g == G) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] = (o + e < j) ? y[e] : (o + e == j ? x[e][e] : a[e]);
+    } else if (g > G) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        T z[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          T s = v[e][p];
+#pragma unroll
+          for (int k = 0; k < p; ++k) s -= x[k][p] * z[k];
+          z[p] = s * rr[p];
+        }
+        T u = a[e];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) u -= z[p] * y[p];
+        a[e] = (4 * g + e <= j) ? u : a[e];
+      }
+    }
+    if (g == G + 1) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) S[4 * g + e + j * LD] = a[e];
+    }
+    wave_fence();
+  }
+  if (l == 0 && bad != 0 && *info == 0) *info = bad;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) S[4 * g + e + j * LD] = a[e];
+  wave_fence();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c.v[r] = S[trow<T, 16>(l, r) + j * LD];
+  wave_fence();
+}
+
+template <class T, int TB>
+TLA_DI void tile_potf2(Tile<T, TB>& c, lds_t<T>* buf, int nv, int base, lds_t<int>* info) {
+  if constexpr (TB == 16) tile_potf2_strip<T>(c, buf, nv, base, info);
+  else tile_potf2_elem<T, TB>(c, buf, nv, base, info);
+}
+
+// ---- Triangular solves with an upper-triangular diagonal tile Xd:
+//   tile_trsm_ut:      c := Xd^{-T} c  (forward substitution down every column)
+//   tile_trsm_right_u: c := c Xd^{-1}  (substitution along every row)
+// Both solve Xd^T y = v for 16 independent vectors v (the columns, or the
+// rows, of c).
+
+// Element schedules (any TB): element k of every vector is final after step
+// k - 1 and is published then.
 template <class T, int TB, class VX>
-TLA_DI void tile_trsm_ut(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) {
+TLA_DI void tile_trsm_ut_elem(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) {
   const int l = lane_id(), j = tcol<TB>(l);
   constexpr int E = Tile<T, TB>::EPL;
-  T xrow[E];
+  T xrow[E], rinv[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int i = trow<T, TB>(l, r);
-    if (i == 0) {
-      c.v[r] = c.v[r] / Xd(0, 0);
+    rinv[r] = T(1) / Xd(i, i);
+  }
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    if (trow<T, TB>(l, r) == 0) {
+      c.v[r] = c.v[r] * rinv[r];
       buf[j] = c.v[r];
     }
   }
@@ -391,15 +644,14 @@ TLA_DI void tile_trsm_ut(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) {
       const T raw = Xd(k, i);
       xrow[r] = i > k ? raw : T(0);
     }
-    const T dk1 = Xd(k + 1, k + 1);
     wave_fence();
     const T y = buf[j];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int i = trow<T, TB>(l, r);
-      if (i > k) c.v[r] -= xrow[r] * y;
+      c.v[r] -= xrow[r] * y;
       if (i == k + 1) {
-        c.v[r] = c.v[r] / dk1;
+        c.v[r] = c.v[r] * rinv[r];
         buf[j] = c.v[r];
       }
     }
@@ -407,18 +659,15 @@ TLA_DI void tile_trsm_ut(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) {
   wave_fence();
 }
 
-// Right solve with an upper-triangular diagonal tile: c := c Xd^{-1}
-// (substitution along every row, left to right); column k of the solution
-// is published when it becomes final.
 template <class T, int TB, class VX>
-TLA_DI void tile_trsm_right_u(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) {
+TLA_DI void tile_trsm_right_u_elem(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) {
   const int l = lane_id(), j = tcol<TB>(l);
   constexpr int E = Tile<T, TB>::EPL;
+  const T rj = T(1) / Xd(j, j);
   if (j == 0) {
-    const T d0 = Xd(0, 0);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-      c.v[r] = c.v[r] / d0;
+      c.v[r] = c.v[r] * rj;
       buf[trow<T, TB>(l, r)] = c.v[r];
     }
   }
@@ -426,24 +675,93 @@ TLA_DI void tile_trsm_right_u(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) {
   for (int k = 0; k < TB - 1; ++k) {
     const T uraw = Xd(k, j);
     const T u = j > k ? uraw : T(0);
-    const T dk1 = Xd(k + 1, k + 1);
     wave_fence();
     T y[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) y[r] = buf[trow<T, TB>(l, r)];
-    if (j > k) {
 #pragma unroll
-      for (int r = 0; r < E; ++r) c.v[r] -= y[r] * u;
-    }
+    for (int r = 0; r < E; ++r) c.v[r] -= y[r] * u;
     if (j == k + 1) {
 #pragma unroll
       for (int r = 0; r < E; ++r) {
-        c.v[r] = c.v[r] / dk1;
+        c.v[r] = c.v[r] * rj;
         buf[trow<T, TB>(l, r)] = c.v[r];
       }
     }
   }
   wave_fence();
+}
+
+// Strip schedule (TB = 16): lane (g, v) = (l >> 4, l & 15) holds elements
+// 4g..4g+3 of vector v.  Block step G: strip G finishes with a 4 x 4 forward
+// substitution in registers and publishes; the strips below subtract
+// Xd^T(strip g, strip G) times it.  RIGHT selects rows of c as the vectors.
+template <class T, bool RIGHT, class VX>
+TLA_DI void tile_trsv_strips(Tile<T, 16>& c, const VX& Xd, lds_t<T>* buf) {
+  const int l = lane_id(), jc = tcol<16>(l), g = l >> 4, v = l & 15;
+  constexpr int LD = 17;
+  constexpr int rs = RIGHT ? LD : 1, cs = RIGHT ? 1 : LD;  // element e of vector v at e*rs + v*cs
+  lds_t<T>* S = buf;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[trow<T, 16>(l, r) + jc * LD] = c.v[r];
+  T dg[4][4], rin[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int b = 0; b < a; ++b) dg[a][b] = Xd(4 * g + b, 4 * g + a);
+    rin[a] = T(1) / Xd(4 * g + a, 4 * g + a);
+  }
+  wave_fence();
+  T y[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) y[a] = S[(4 * g + a) * rs + v * cs];
+#pragma unroll
+  for (int G = 0; G < 4; ++G) {
+    if (g == G) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        T acc = y[a];
+#pragma unroll
+        for (int b = 0; b < a; ++b) acc -= dg[a][b] * y[b];
+        y[a] = acc * rin[a];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) S[(4 * G + a) * rs + v * cs] = y[a];
+    }
+    if (G == 3) break;
+    // Xd^T(4g + a, 4G + b) = Xd(4G + b, 4g + a), used by the strips g > G
+    T cf[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) cf[a][b] = Xd(4 * G + b, 4 * g + a);
+    wave_fence();
+    T z[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) z[b] = S[(4 * G + b) * rs + v * cs];
+    if (g > G) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) y[a] -= cf[a][b] * z[b];
+    }
+  }
+  wave_fence();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c.v[r] = S[trow<T, 16>(l, r) + jc * LD];
+  wave_fence();
+}
+
+template <class T, int TB, class VX>
+TLA_DI void tile_trsm_ut(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) {
+  if constexpr (TB == 16) tile_trsv_strips<T, false>(c, Xd, buf);
+  else tile_trsm_ut_elem<T, TB>(c, Xd, buf);
+}
+
+template <class T, int TB, class VX>
+TLA_DI void tile_trsm_right_u(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) {
+  if constexpr (TB == 16) tile_trsv_strips<T, true>(c, Xd, buf);
+  else tile_trsm_right_u_elem<T, TB>(c, Xd, buf);
 }
 
 }  // namespace tla
