@@ -124,17 +124,37 @@ TLA_DI void egress(double* Gg, int ldg, int n, const T* Wg, int ldw, int part) {
   }
 }
 
-// first zero denominator d_ij = a_i + b_j (column-major index + 1) into *info:
-// each thread keeps its own minimum and publishes it once, so the loads of
-// the loop carry no dependence on the atomic
+// value of v held by lane l of this wavefront (l uniform across the wave)
+TLA_DI double read_lane(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// First zero denominator d_ij = a_ii + b_jj (column-major index i + j n, plus
+// 1) into *info; lower_only restricts the scan to i >= j.  The (i, j) plane
+// is cut into 64 x 64 chunks handed to the waves; a wave loads the two
+// diagonal pieces of its chunk once, one element per lane, and walks the
+// columns with b_jj broadcast from lane j.  Each thread keeps its own minimum
+// and publishes it once.
 template <class VA, class VB, class IP>
 TLA_DI void scan_zero_denoms(const VA& A, const VB& B, int n, bool lower_only, IP info) {
   int best = INT_MAX;
-  const int nw = blockDim.x >> 6;
-  for (int j = wave_id(); j < n; j += nw) {
-    const auto bj = B(j, j);
-    for (int i = lower_only ? j + lane_id() : lane_id(); i < n; i += 64) {
-      if (A(i, i) + bj == 0.0) best = min(best, 1 + i + j * n);
+  const int nw = blockDim.x >> 6, lane = lane_id();
+  const int nc = (n + 63) >> 6;
+  for (int t = wave_id(); t < nc * nc; t += nw) {
+    const int ic = t % nc, jc = t / nc;
+    if (lower_only && ic < jc) continue;
+    const int i = 64 * ic + lane, jl = 64 * jc + lane;
+    const int ii = i < n ? i : n - 1, jj = jl < n ? jl : n - 1;
+    const double ai = A(ii, ii);
+    const double bl = B(jj, jj);
+    const int jn = n - 64 * jc < 64 ? n - 64 * jc : 64;
+    for (int q = 0; q < jn; ++q) {
+      const double bj = read_lane(bl, q);
+      const int j = 64 * jc + q;
+      if (i < n && (!lower_only || i >= j) && ai + bj == 0.0) best = min(best, 1 + i + j * n);
     }
   }
   if (best != INT_MAX) atomicMin(info, best);
