@@ -133,14 +133,17 @@ TLA_DI double read_lane(double v, int l) {
 }
 
 // First zero denominator d_ij = a_ii + b_jj (column-major index i + j n, plus
-// 1) into *info; lower_only restricts the scan to i >= j.  The (i, j) plane
-// is cut into 64 x 64 chunks handed to the waves; a wave loads the two
+// 1) into *info; lower_only restricts the scan to i >= j.  With F32 the same
+// pass also reports (return value) whether some denominator is zero once the
+// two diagonal entries are rounded to FP32 and added in FP32.  The (i, j)
+// plane is cut into 64 x 64 chunks handed to the waves; a wave loads the two
 // diagonal pieces of its chunk once, one element per lane, and walks the
 // columns with b_jj broadcast from lane j.  Each thread keeps its own minimum
 // and publishes it once.
-template <class VA, class VB, class IP>
-TLA_DI void scan_zero_denoms(const VA& A, const VB& B, int n, bool lower_only, IP info) {
+template <bool F32 = false, class VA, class VB, class IP>
+TLA_DI bool scan_zero_denoms(const VA& A, const VB& B, int n, bool lower_only, IP info) {
   int best = INT_MAX;
+  bool zero32 = false;
   const int nw = blockDim.x >> 6, lane = lane_id();
   const int nc = (n + 63) >> 6;
   for (int t = wave_id(); t < nc * nc; t += nw) {
@@ -150,14 +153,52 @@ TLA_DI void scan_zero_denoms(const VA& A, const VB& B, int n, bool lower_only, I
     const int ii = i < n ? i : n - 1, jj = jl < n ? jl : n - 1;
     const double ai = A(ii, ii);
     const double bl = B(jj, jj);
+    const float ai32 = float(ai);
     const int jn = n - 64 * jc < 64 ? n - 64 * jc : 64;
     for (int q = 0; q < jn; ++q) {
       const double bj = read_lane(bl, q);
       const int j = 64 * jc + q;
-      if (i < n && (!lower_only || i >= j) && ai + bj == 0.0) best = min(best, 1 + i + j * n);
+      const bool live = i < n && (!lower_only || i >= j);
+      if (live && ai + bj == 0.0) best = min(best, 1 + i + j * n);
+      if constexpr (F32) zero32 = zero32 || (live && ai32 + float(bj) == 0.0f);
     }
   }
   if (best != INT_MAX) atomicMin(info, best);
+  return zero32;
+}
+
+// Squared Frobenius norm share of this thread for the part of an n x n
+// global matrix selected by `part` (0 full, -1 lower, +1 upper); sym counts
+// off-diagonal entries twice.  Loads are batched as in ingest.
+template <int NW>
+TLA_DI double gnorm2(const double* Gg, int ldg, int n, int part, bool sym = false) {
+  constexpr int U = 8;
+  const int w = wave_id(), l = lane_id();
+  const gbl_t<double>* G = to_gbl(Gg);
+  double ss = 0.0;
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int i = i0 + l;
+    for (int jb = w; jb < n; jb += NW * U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = jb + u * NW;
+        const int jc = j < n ? j : n - 1;
+        int ic = i < n ? i : n - 1;
+        if (part < 0) ic = ic > jc ? ic : jc;
+        if (part > 0) ic = ic < jc ? ic : jc;
+        const double raw = G[ic + (size_t)jc * ldg];
+        const bool keep = i < n && j < n && (part == 0 || (part < 0 ? i >= j : i <= j));
+        v[u] = keep ? raw : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = jb + u * NW;
+        ss += (sym && i != j ? 2.0 : 1.0) * v[u] * v[u];
+      }
+    }
+  }
+  return ss;
 }
 
 // One instance's operands and result slots (see KArgs for the roles).

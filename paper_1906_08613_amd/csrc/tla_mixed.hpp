@@ -147,25 +147,15 @@ TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
     sl = ingest<float, NW>(m.A1, ld, np, Lg, ldl, n, -1, 0.0f);
     su = ingest<float, NW>(m.A2, ld, np, Ug, ldu, n, +1, 0.0f);
   } else {
-    for (int j = wave_id(); j < n; j += NW)
-      for (int i = lane_id(); i < n; i += 64) {
-        const double lv = L64(i, j), uv = U64(i, j);
-        sl += lv * lv;
-        su += uv * uv;
-      }
+    sl = gnorm2<NW>(Lg, ldl, n, -1);
+    su = gnorm2<NW>(Ug, ldu, n, +1);
   }
   const double nc = sqrt(block_sum<NW>(sc, m.red));
   const double nl = sqrt(block_sum<NW>(sl, m.red));
   const double nu = sqrt(block_sum<NW>(su, m.red));
   int bad = (nc - nc != 0.0 || nl - nl != 0.0 || nu - nu != 0.0) ? TLA_STAT_NONFINITE : 0;
   // exact zero denominators (FP64) decide info; FP32 ones only force the FP64 path
-  scan_zero_denoms(L64, U64, n, false, m.info);
-  int lo_zero = 0;
-  for (int j = wave_id(); j < n; j += NW) {
-    const float uj = float(U64(j, j));
-    for (int i = lane_id(); i < n; i += 64)
-      if (float(L64(i, i)) + uj == 0.0f) lo_zero = TLA_STAT_BREAKDOWN;
-  }
+  const int lo_zero = scan_zero_denoms<true>(L64, U64, n, false, m.info) ? TLA_STAT_BREAKDOWN : 0;
   bad |= block_or<NW>(lo_zero | bad, m.ired);
   st.flags |= bad;
   const int info0 = *m.info == INT_MAX ? 0 : *m.info;
@@ -257,24 +247,14 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
   if constexpr (LU_LDS) {
     sl = ingest<float, NW>(m.A1, ld, np, Lg, ldl, n, -1, 0.0f);
   } else {
-    for (int j = wave_id(); j < n; j += NW)
-      for (int i = lane_id(); i < n; i += 64) {
-        const double lv = L64(i, j);
-        sl += lv * lv;
-      }
+    sl = gnorm2<NW>(Lg, ldl, n, -1);
   }
   __syncthreads();
   mirror_lower(m.W, ld, np);
   const double ns = sqrt(block_sum<NW>(ss, m.red));
   const double nl = sqrt(block_sum<NW>(sl, m.red));
   int bad = (ns - ns != 0.0 || nl - nl != 0.0) ? TLA_STAT_NONFINITE : 0;
-  scan_zero_denoms(L64, L64, n, true, m.info);
-  int lo_zero = 0;
-  for (int j = wave_id(); j < n; j += NW) {
-    const float lj = float(L64(j, j));
-    for (int i = j + lane_id(); i < n; i += 64)
-      if (float(L64(i, i)) + lj == 0.0f) lo_zero = TLA_STAT_BREAKDOWN;
-  }
+  const int lo_zero = scan_zero_denoms<true>(L64, L64, n, true, m.info) ? TLA_STAT_BREAKDOWN : 0;
   bad |= block_or<NW>(lo_zero | bad, m.ired);
   st.flags |= bad;
   const int info0 = *m.info == INT_MAX ? 0 : *m.info;

@@ -126,9 +126,19 @@ TLA_DI void potrf_blocked(const VA& A, const Ctx<T>& cx) {
 //   SYL_CE  block columns, eager: sweep the column; C_{>J} -= X_J U_{J,>J}.
 enum { SYL_WF = 0, SYL_RL = 1, SYL_RE = 2, SYL_CL = 3, SYL_CE = 4, SYL_NVAR = 5 };
 
+// Diagonal-tile coefficients of tile (I, J) (L_II and U_JJ), fetched before
+// the tile's updates so that their loads overlap the products.
+template <class T, int TB, class VL, class VU>
+TLA_DI auto syl_tile_fetch(const VL& L, const VU& U, int I, int J) {
+  return sylv_fetch<T, TB>(L.sub(I * TB, I * TB), U.sub(J * TB, J * TB));
+}
+template <class T, int TB, class K>
+TLA_DI void syl_tile_solve_k(Tile<T, TB>& c, const K& k, const Ctx<T>& cx, int I, int J) {
+  sylv_solve<T, TB>(c, k, cx.wbuf, cx.n - I * TB, cx.n - J * TB);
+}
 template <class T, int TB, class VL, class VU>
 TLA_DI void syl_tile_solve(Tile<T, TB>& c, const VL& L, const VU& U, const Ctx<T>& cx, int I, int J) {
-  tile_sylv<T, TB>(c, L.sub(I * TB, I * TB), U.sub(J * TB, J * TB), cx.wbuf, cx.n - I * TB, cx.n - J * TB);
+  syl_tile_solve_k<T, TB>(c, syl_tile_fetch<T, TB>(L, U, I, J), cx, I, J);
 }
 
 template <class T, int TB, int ENG, int NW, int VAR, class VX, class VL, class VU>
@@ -141,11 +151,12 @@ TLA_DI void trsyl_blocked(const VX& X, const VL& L, const VU& U, const Ctx<T>& c
       const int hi = d < nt - 1 ? d : nt - 1;
       for (int I = lo + w; I <= hi; I += NW) {
         const int J = d - I;
+        const auto k = syl_tile_fetch<T, TB>(L, U, I, J);
         Tile<T, TB> c;
         tload(c, X.sub(I * TB, J * TB));
         gemm_sum<G>(c, 0, I, [&](int K) { return L.sub(I * TB, K * TB); }, [&](int K) { return X.sub(K * TB, J * TB); });
         gemm_sum<G>(c, 0, J, [&](int K) { return X.sub(I * TB, K * TB); }, [&](int K) { return U.sub(K * TB, J * TB); });
-        syl_tile_solve<T, TB>(c, L, U, cx, I, J);
+        syl_tile_solve_k<T, TB>(c, k, cx, I, J);
         tstore(c, X.sub(I * TB, J * TB));
       }
       __syncthreads();
@@ -163,10 +174,11 @@ TLA_DI void trsyl_blocked(const VX& X, const VL& L, const VU& U, const Ctx<T>& c
       }
       if (w == 0) {
         for (int J = 0; J < nt; ++J) {
+          const auto k = syl_tile_fetch<T, TB>(L, U, I, J);
           Tile<T, TB> c;
           tload(c, X.sub(I * TB, J * TB));
           gemm_sum<G>(c, 0, J, [&](int K) { return X.sub(I * TB, K * TB); }, [&](int K) { return U.sub(K * TB, J * TB); });
-          syl_tile_solve<T, TB>(c, L, U, cx, I, J);
+          syl_tile_solve_k<T, TB>(c, k, cx, I, J);
           tstore(c, X.sub(I * TB, J * TB));
         }
       }
@@ -196,10 +208,11 @@ TLA_DI void trsyl_blocked(const VX& X, const VL& L, const VU& U, const Ctx<T>& c
       }
       if (w == 0) {
         for (int I = 0; I < nt; ++I) {
+          const auto k = syl_tile_fetch<T, TB>(L, U, I, J);
           Tile<T, TB> c;
           tload(c, X.sub(I * TB, J * TB));
           gemm_sum<G>(c, 0, I, [&](int K) { return L.sub(I * TB, K * TB); }, [&](int K) { return X.sub(K * TB, J * TB); });
-          syl_tile_solve<T, TB>(c, L, U, cx, I, J);
+          syl_tile_solve_k<T, TB>(c, k, cx, I, J);
           tstore(c, X.sub(I * TB, J * TB));
         }
       }
@@ -232,9 +245,13 @@ TLA_DI void trsyl_blocked(const VX& X, const VL& L, const VU& U, const Ctx<T>& c
 //           below it, then the symmetric rank-2b update of the trailing part.
 enum { LYA_WF = 0, LYA_RL = 1, LYA_RE = 2, LYA_NVAR = 3 };
 
-template <class T, int TB, class VX, class VL>
-TLA_DI void lya_tile_solve(Tile<T, TB>& c, const VX& X, const VL& L, const Ctx<T>& cx, int I, int J) {
-  tile_sylv<T, TB>(c, L.sub(I * TB, I * TB), L.sub(J * TB, J * TB).t(), cx.wbuf, cx.n - I * TB, cx.n - J * TB);
+template <class T, int TB, class VL>
+TLA_DI auto lya_tile_fetch(const VL& L, int I, int J) {
+  return sylv_fetch<T, TB>(L.sub(I * TB, I * TB), L.sub(J * TB, J * TB).t());
+}
+template <class T, int TB, class VX, class K>
+TLA_DI void lya_tile_solve_k(Tile<T, TB>& c, const VX& X, const K& k, const Ctx<T>& cx, int I, int J) {
+  sylv_solve<T, TB>(c, k, cx.wbuf, cx.n - I * TB, cx.n - J * TB);
   if (I == J) {
     // store the lower triangle into both halves: the tile becomes exactly symmetric
     const int l = lane_id(), j = tcol<TB>(l);
@@ -250,6 +267,10 @@ TLA_DI void lya_tile_solve(Tile<T, TB>& c, const VX& X, const VL& L, const Ctx<T
   } else {
     tstore(c, X.sub(I * TB, J * TB));
   }
+}
+template <class T, int TB, class VX, class VL>
+TLA_DI void lya_tile_solve(Tile<T, TB>& c, const VX& X, const VL& L, const Ctx<T>& cx, int I, int J) {
+  lya_tile_solve_k<T, TB>(c, X, lya_tile_fetch<T, TB>(L, I, J), cx, I, J);
 }
 
 // column-side lazy update: c -= sum_{K in [k0,k1)} L_IK X~_KJ, X~_KJ = X_KJ (K >= J) or X_JK^T
@@ -276,11 +297,12 @@ TLA_DI void trlyap_blocked(const VX& X, const VL& L, const Ctx<T>& cx) {
       const int hi = d < nt - 1 ? d : nt - 1;
       for (int I = lo + w; I <= hi; I += NW) {
         const int J = d - I;
+        const auto k = lya_tile_fetch<T, TB>(L, I, J);
         Tile<T, TB> c;
         tload(c, X.sub(I * TB, J * TB));
         lya_colside<T, TB, ENG>(c, X, L, I, J, 0, I);
         lya_rowside<T, TB, ENG>(c, X, L, I, J, 0, J);
-        lya_tile_solve<T, TB>(c, X, L, cx, I, J);
+        lya_tile_solve_k<T, TB>(c, X, k, cx, I, J);
       }
       __syncthreads();
     }
@@ -297,11 +319,12 @@ TLA_DI void trlyap_blocked(const VX& X, const VL& L, const Ctx<T>& cx) {
       __syncthreads();
       if (w == 0) {
         for (int J = 0; J <= I; ++J) {
+          const auto k = lya_tile_fetch<T, TB>(L, I, J);
           Tile<T, TB> c;
           tload(c, X.sub(I * TB, J * TB));
           if (J == I) lya_colside<T, TB, ENG>(c, X, L, I, J, 0, I);
           lya_rowside<T, TB, ENG>(c, X, L, I, J, 0, J);
-          lya_tile_solve<T, TB>(c, X, L, cx, I, J);
+          lya_tile_solve_k<T, TB>(c, X, k, cx, I, J);
         }
       }
       __syncthreads();
@@ -314,9 +337,10 @@ TLA_DI void trlyap_blocked(const VX& X, const VL& L, const Ctx<T>& cx) {
         lya_tile_solve<T, TB>(c, X, L, cx, K, K);
         // tiles below: L_II X_IK + X_IK L_KK^T = S_IK - L_IK X_KK - sum_{K<P<I} L_IP X_PK
         for (int I = K + 1; I < nt; ++I) {
+          const auto k = lya_tile_fetch<T, TB>(L, I, K);
           tload(c, X.sub(I * TB, K * TB));
           gemm_sum<G>(c, K, I, [&](int P) { return L.sub(I * TB, P * TB); }, [&](int P) { return X.sub(P * TB, K * TB); });
-          lya_tile_solve<T, TB>(c, X, L, cx, I, K);
+          lya_tile_solve_k<T, TB>(c, X, k, cx, I, K);
         }
       }
       __syncthreads();

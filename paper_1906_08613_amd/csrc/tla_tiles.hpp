@@ -239,8 +239,8 @@ struct Gemm<T, TB, ENG_VALU> {
 
 // c -= sum_{K = k0}^{k1 - 1} fa(K) * fb(K), where fa / fb return the operand
 // views of step K.  (Fetching step K + 1's fragments ahead of step K's
-// products was measured slower: it raised register use and lowered the
-// number of resident waves.)
+// products was measured slower, also with operands read through the caches:
+// it raised register use and lowered the number of resident waves.)
 template <class G, class Tl, class FA, class FB>
 TLA_DI void gemm_sum(Tl& c, int k0, int k1, const FA& fa, const FB& fb) {
   for (int K = k0; K < k1; ++K) G::sub(c, fa(K), fb(K));
@@ -353,8 +353,37 @@ TLA_DI int blk2_index(int i, int j) {  // element (i, j) of a tile stored as 2 x
   return 4 * ((TB / 2) * (i >> 1) + (j >> 1)) + 2 * (i & 1) + (j & 1);
 }
 
+// Coefficients one lane needs for the 2 x 2 block schedule: its block of Lt
+// and of Ut and the diagonal blocks of its row and column.  Fetched apart from
+// the solve so that callers can issue these loads before the tile's updates.
+template <class T>
+struct Blk2Coef {
+  T lv[4], uv[4];
+  T l00, l10, l11, u00, u01, u11;
+};
+
 template <class T, class VL, class VU>
-TLA_DI void tile_sylv_blk2(Tile<T, 16>& c, const VL& Lt, const VU& Ut, lds_t<T>* buf, int ni, int nj) {
+TLA_DI Blk2Coef<T> blk2_fetch(const VL& Lt, const VU& Ut) {
+  const int l = lane_id(), i0 = 2 * (l >> 3), j0 = 2 * (l & 7);
+  Blk2Coef<T> k;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      k.lv[2 * a + b] = Lt(i0 + a, j0 + b);
+      k.uv[2 * a + b] = Ut(i0 + a, j0 + b);
+    }
+  k.l00 = Lt(i0, i0);
+  k.l10 = Lt(i0 + 1, i0);
+  k.l11 = Lt(i0 + 1, i0 + 1);
+  k.u00 = Ut(j0, j0);
+  k.u01 = Ut(j0, j0 + 1);
+  k.u11 = Ut(j0 + 1, j0 + 1);
+  return k;
+}
+
+template <class T>
+TLA_DI void tile_sylv_blk2(Tile<T, 16>& c, const Blk2Coef<T>& k, lds_t<T>* buf, int ni, int nj) {
   const int l = lane_id(), I = l >> 3, J = l & 7;
   lds_t<T>* Lb = buf;        // block (I, K) at 4 (8 I + K): Lt's block if K < I, else 0
   lds_t<T>* Ub = buf + 256;  // block (K, J) at 4 (8 K + J): Ut's block if K < J, else 0
@@ -372,13 +401,10 @@ TLA_DI void tile_sylv_blk2(Tile<T, 16>& c, const VL& Lt, const VU& Ut, lds_t<T>*
   // the reads above are served before these writes (same wave, LDS in order)
   const int i0 = 2 * I, j0 = 2 * J;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const T lv = Lt(i0 + a, j0 + b), uv = Ut(i0 + a, j0 + b);
-      Lb[4 * l + 2 * a + b] = J < I ? lv : T(0);
-      Ub[4 * l + 2 * a + b] = I < J ? uv : T(0);
-    }
+  for (int e = 0; e < 4; ++e) {
+    Lb[4 * l + e] = J < I ? k.lv[e] : T(0);
+    Ub[4 * l + e] = I < J ? k.uv[e] : T(0);
+  }
   if (l < 8) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -386,8 +412,7 @@ TLA_DI void tile_sylv_blk2(Tile<T, 16>& c, const VL& Lt, const VU& Ut, lds_t<T>*
       rb[4 * l + e] = T(0);
     }
   }
-  const T l00 = Lt(i0, i0), l10 = Lt(i0 + 1, i0), l11 = Lt(i0 + 1, i0 + 1);
-  const T u00 = Ut(j0, j0), u01 = Ut(j0, j0 + 1), u11 = Ut(j0 + 1, j0 + 1);
+  const T l00 = k.l00, l10 = k.l10, l11 = k.l11, u00 = k.u00, u01 = k.u01, u11 = k.u11;
   const bool r0 = i0 < ni, r1 = i0 + 1 < ni, c0 = j0 < nj, c1 = j0 + 1 < nj;
   const T q00 = (r0 && c0) ? T(1) / (l00 + u00) : T(0);
   const T q01 = (r0 && c1) ? T(1) / (l00 + u11) : T(0);
@@ -413,7 +438,7 @@ TLA_DI void tile_sylv_blk2(Tile<T, 16>& c, const VL& Lt, const VU& Ut, lds_t<T>*
 #pragma unroll 1
   for (int D = 0; D < 14; ++D) {
     int K = D - J, K2 = D - I;
-    K = (K >= 0 && K < 8) ? K : I;     // out of range: a zero block of Lb
+    K = (K >= 0 && K < 8) ? K : I;  // out of range: a zero block of Lb
     K2 = (K2 >= 0 && K2 < 8) ? K2 : J;
     T lk[4], uk[4];
 #pragma unroll
@@ -455,10 +480,29 @@ TLA_DI void tile_sylv_blk2(Tile<T, 16>& c, const VL& Lt, const VU& Ut, lds_t<T>*
   wave_fence();
 }
 
+// Two-phase interface: sylv_fetch issues the coefficient loads of a diagonal
+// tile pair, sylv_solve solves the tile with them.
+template <class VL, class VU>
+struct ViewPair {
+  VL L;
+  VU U;
+};
+
+template <class T, int TB, class VL, class VU>
+TLA_DI auto sylv_fetch(const VL& Lt, const VU& Ut) {
+  if constexpr (TB == 16) return blk2_fetch<T>(Lt, Ut);
+  else return ViewPair<VL, VU>{Lt, Ut};
+}
+
+template <class T, int TB, class K>
+TLA_DI void sylv_solve(Tile<T, TB>& c, const K& k, lds_t<T>* buf, int ni, int nj) {
+  if constexpr (TB == 16) tile_sylv_blk2<T>(c, k, buf, ni, nj);
+  else tile_sylv_elem<T, TB>(c, k.L, k.U, buf, ni, nj);
+}
+
 template <class T, int TB, class VL, class VU>
 TLA_DI void tile_sylv(Tile<T, TB>& c, const VL& Lt, const VU& Ut, lds_t<T>* buf, int ni, int nj) {
-  if constexpr (TB == 16) tile_sylv_blk2<T>(c, Lt, Ut, buf, ni, nj);
-  else tile_sylv_elem<T, TB>(c, Lt, Ut, buf, ni, nj);
+  sylv_solve<T, TB>(c, sylv_fetch<T, TB>(Lt, Ut), buf, ni, nj);
 }
 
 // ---- Upper Cholesky of a diagonal tile held in c (only j >= i is used and
