@@ -34,18 +34,32 @@ bool plan_valid(int op, const tla_plan& p) {
   if (p.engine != 0 && p.engine != 1) return false;
   if (p.tile == 8 && p.engine == 1) return false;
   if (p.waves != 1 && p.waves != 2 && p.waves != 4) return false;
-  // place 2 (FP64 solution in the workspace) only exists for the mixed kernels;
-  // the launcher reports it unsupported for FP64
-  if (p.place < 0 || p.place > 2) return false;
+  // place 2 (FP64 solution in the workspace) only exists for the mixed kernels
+  // and place 3 (in place in global memory) only for FP64; the launcher
+  // reports the other precision unsupported
+  if (p.place < 0 || p.place > 3) return false;
   if (op == TLA_POTRF && p.place == 1) return false;
+  if (p.place == 3 && !(p.tile == 16 && p.engine == 1)) return false;
   return true;
 }
 
-// candidates: variant x (tile, engine) x waves x coefficient placement
+// candidates: variant x (tile, engine) x waves x coefficient placement 0..2,
+// then variant x waves with placement 3 (16 x 16 matrix-core tiles only)
 static int num_places(int op) { return op == TLA_POTRF ? 2 : 3; }
-int num_candidates(int op) { return num_variants(op) * kNumTE * kNumNW * num_places(op); }
+static int num_candidates_lds(int op) { return num_variants(op) * kNumTE * kNumNW * num_places(op); }
+int num_candidates(int op) { return num_candidates_lds(op) + num_variants(op) * kNumNW; }
 bool candidate(int op, int i, tla_plan* p) {
   if (i < 0 || i >= num_candidates(op)) return false;
+  if (i >= num_candidates_lds(op)) {
+    i -= num_candidates_lds(op);
+    const int nwi = i % kNumNW;
+    p->variant = i / kNumNW;
+    p->tile = 16;
+    p->engine = 1;
+    p->waves = nwi == 0 ? 1 : (nwi == 1 ? 2 : 4);
+    p->place = 3;
+    return true;
+  }
   const int np = num_places(op);
   p->place = i % np;
   if (op == TLA_POTRF && p->place == 1) p->place = 2;  // potrf: 0 or 2
@@ -148,7 +162,8 @@ extern "C" tla_status tla_set_refine(tla_handle h, double tau, int max_iter) {
 namespace tla {
 
 // LDS bytes for one instance of `op` with ntmax tiles per dimension.
-// FP64 kernels, placement 0: coefficients and X in LDS, 1: X only.
+// FP64 kernels, placement 0: coefficients and X in LDS, 1: X only, 3: the
+// tile solvers' scratch only (X in place in global memory).
 // Mixed kernels: FP32 work matrix W (+ FP32 coefficients / factor copy) and
 // the FP64 solution (placement < last) in LDS; see tla_registry.h.
 size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int pl) {
@@ -156,6 +171,7 @@ size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int pl) {
   const size_t mat8 = np * (np + 1) * 8, mat4 = np * (np + 1) * 4;
   const size_t scr = (size_t)nw * wave_scratch(tb) * 8 + 16 + 8 * (nw + 4);
   if (prec == TLA_F64) {
+    if (pl == 3) return inplace_lds_bytes(nw);
     if (op == TLA_POTRF) return mat8 + scr;
     if (op == TLA_TRSYL) return mat8 * (pl == 0 ? 3 : 1) + scr;
     return mat8 * (pl == 0 ? 2 : 1) + scr;
@@ -192,6 +208,7 @@ static tla_status ensure_buffers(tla_ctx* h, size_t work_bytes, int batch) {
 static KFn kernel_for(int op, int prec, const tla_plan& p, int pl) {
   const int te = te_index(p.tile, p.engine), nwi = nw_index(p.waves);
   if (prec == TLA_F64) {
+    if (pl == 3) return inplace_kernel(op, p.variant, nwi);
     if (op == TLA_POTRF) return potrf_f64_kernel(p.variant, te, nwi);
     if (op == TLA_TRSYL) return trsyl_f64_kernel(p.variant, te, nwi, pl == 0);
     return trlyap_f64_kernel(p.variant, te, nwi, pl == 0);
@@ -201,12 +218,16 @@ static KFn kernel_for(int op, int prec, const tla_plan& p, int pl) {
   return trlyap_mixed_kernel(prec, p.variant, te, nwi, pl);
 }
 
-// First placement whose LDS fits: returns -1 when none does.
+// First placement whose LDS fits: returns -1 when none does.  FP64 runs
+// placements 0 / 1 (potrf 0) and 3, the mixed precisions 0 / 1 / 2 (potrf
+// 0 / 2); the search moves to larger placements of the same family.
 int choose_placement(tla_ctx* h, int op, int prec, const tla_plan& p, int ntmax, size_t* lds) {
-  const int last = prec == TLA_F64 ? (op == TLA_POTRF ? 0 : 1) : 2;
+  const int last = prec == TLA_F64 ? 3 : 2;
   if (p.place > last) return -1;
   for (int pl = p.place; pl <= last; ++pl) {
-    if (prec != TLA_F64 && op == TLA_POTRF && pl == 1) continue;
+    if (op == TLA_POTRF && pl == 1) continue;
+    if (prec == TLA_F64 && pl == 2) continue;
+    if (pl == 3 && !(p.tile == 16 && p.engine == 1)) continue;
     const size_t b = lds_bytes(op, prec, p.tile, p.waves, ntmax, pl);
     if (b <= (size_t)h->lds_limit) { *lds = b; return pl; }
   }

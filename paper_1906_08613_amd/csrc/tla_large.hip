@@ -1,7 +1,10 @@
-// Large sizes (n > 128): one workgroup of 16 wavefronts per instance, the
-// matrices stay in global memory and are solved in place; only the tile
-// solvers' scratch lives in LDS.  Tiles stream through registers and the
-// matrix cores, the same blocked variants as for the LDS-resident sizes.
+// In-place kernels: the matrices stay in global memory and are solved in
+// place; only the tile solvers' scratch lives in LDS.  Tiles stream through
+// registers and the matrix cores (16 x 16 tiles), the same blocked variants as
+// for the LDS-resident kernels.  Used for the large sizes (n > 128, one
+// workgroup of 16 wavefronts per instance) and, with 1, 2 or 4 wavefronts, as
+// placement 3 of the smaller sizes: with no matrix in LDS many more instances
+// are resident per compute unit, and the caches serve the tile traffic.
 #include "tla_kernels.hpp"
 #include "tla_registry.h"
 
@@ -50,108 +53,126 @@ TLA_DI IOView<T> ioview(double* p, int ld, int n, bool upper_only) { return IOVi
 
 constexpr int kLargeTB = 16, kLargeNW = 16;
 
+
+template <int NW>
 TLA_DI void large_ctx_init(unsigned char* smem, Ctx<double>& cx, int n, int*& s_info, int init) {
   double* wb = reinterpret_cast<double*>(smem);
-  s_info = reinterpret_cast<int*>(wb + kLargeNW * wave_scratch(kLargeTB));
+  s_info = reinterpret_cast<int*>(wb + NW * wave_scratch(kLargeTB));
   if (threadIdx.x == 0) *s_info = init;
   __syncthreads();
   cx = Ctx<double>{n, (n + kLargeTB - 1) / kLargeTB, to_lds(wb + wave_id() * wave_scratch(kLargeTB)), to_lds(s_info)};
 }
 
-template <int VAR>
-__global__ __launch_bounds__(kLargeNW * 64) void k_potrf_large(KArgs g) {
+template <int NW, int VAR>
+__global__ __launch_bounds__(NW * 64) void k_potrf_large(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Inst in = fetch_uniform(g, blockIdx.x);
   int n;
+  if (skip_unflagged(g, in)) return;
   if (!validate(in, g.n_max, n)) return;
   Ctx<double> cx;
   int* s_info;
-  large_ctx_init(smem, cx, n, s_info, 0);
-  potrf_blocked<double, kLargeTB, ENG_MFMA, kLargeNW, VAR>(ioview<double>(in.c, in.ldc, n, true), cx);
+  large_ctx_init<NW>(smem, cx, n, s_info, 0);
+  potrf_blocked<double, kLargeTB, ENG_MFMA, NW, VAR>(ioview<double>(in.c, in.ldc, n, true), cx);
   __syncthreads();
   if (threadIdx.x == 0) {
     *in.info = *s_info;
-    if (in.stat) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
+    if (in.stat && !g.only_flagged) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
   }
 }
 
-template <int VAR>
-__global__ __launch_bounds__(kLargeNW * 64) void k_trsyl_large(KArgs g) {
+template <int NW, int VAR>
+__global__ __launch_bounds__(NW * 64) void k_trsyl_large(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Inst in = fetch_uniform(g, blockIdx.x);
   int n;
+  if (skip_unflagged(g, in)) return;
   if (!validate(in, g.n_max, n)) return;
   Ctx<double> cx;
   int* s_info;
-  large_ctx_init(smem, cx, n, s_info, INT_MAX);
+  large_ctx_init<NW>(smem, cx, n, s_info, INT_MAX);
   const GView<double> L = gview<double>(in.a, in.lda, n, -1);
   const GView<double> U = gview<double>(in.b, in.ldb, n, +1);
   scan_zero_denoms(L, U, n, false, s_info);
-  trsyl_blocked<double, kLargeTB, ENG_MFMA, kLargeNW, VAR>(ioview<double>(in.c, in.ldc, n, false), L, U, cx);
+  trsyl_blocked<double, kLargeTB, ENG_MFMA, NW, VAR>(ioview<double>(in.c, in.ldc, n, false), L, U, cx);
   __syncthreads();
   if (threadIdx.x == 0) {
     *in.info = *s_info == INT_MAX ? 0 : *s_info;
-    if (in.stat) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
+    if (in.stat && !g.only_flagged) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
   }
 }
 
 // mirrors the lower triangle of the caller's n x n matrix into its upper one
+template <int NW>
 TLA_DI void mirror_global(double* p, int ld, int n) {
   gbl_t<double>* q = to_gbl(p);
-  for (int j = wave_id(); j < n; j += kLargeNW)
+  for (int j = wave_id(); j < n; j += NW)
     for (int i = lane_id(); i < j; i += 64) q[i + (size_t)j * ld] = q[j + (size_t)i * ld];
 }
 
-template <int VAR>
-__global__ __launch_bounds__(kLargeNW * 64) void k_trlyap_large(KArgs g) {
+template <int NW, int VAR>
+__global__ __launch_bounds__(NW * 64) void k_trlyap_large(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Inst in = fetch_uniform(g, blockIdx.x);
   int n;
+  if (skip_unflagged(g, in)) return;
   if (!validate(in, g.n_max, n)) return;
   Ctx<double> cx;
   int* s_info;
-  large_ctx_init(smem, cx, n, s_info, INT_MAX);
+  large_ctx_init<NW>(smem, cx, n, s_info, INT_MAX);
   const GView<double> L = gview<double>(in.a, in.lda, n, -1);
   scan_zero_denoms(L, L, n, true, s_info);
   // S is given by its lower triangle; the diagonal tiles are used in full
-  mirror_global(in.c, in.ldc, n);
+  mirror_global<NW>(in.c, in.ldc, n);
   __syncthreads();
-  trlyap_blocked<double, kLargeTB, ENG_MFMA, kLargeNW, VAR>(ioview<double>(in.c, in.ldc, n, false), L, cx);
+  trlyap_blocked<double, kLargeTB, ENG_MFMA, NW, VAR>(ioview<double>(in.c, in.ldc, n, false), L, cx);
   __syncthreads();
-  mirror_global(in.c, in.ldc, n);
+  mirror_global<NW>(in.c, in.ldc, n);
   __syncthreads();
   if (threadIdx.x == 0) {
     *in.info = *s_info == INT_MAX ? 0 : *s_info;
-    if (in.stat) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
+    if (in.stat && !g.only_flagged) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
   }
 }
 
-KFn large_kernel(int op, int var) {
+template <int NW>
+static KFn inplace_kernel_nw(int op, int var) {
   if (op == TLA_POTRF) {
     switch (var) {
-      case 0: return reinterpret_cast<KFn>(&k_potrf_large<0>);
-      case 1: return reinterpret_cast<KFn>(&k_potrf_large<1>);
-      case 2: return reinterpret_cast<KFn>(&k_potrf_large<2>);
+      case 0: return reinterpret_cast<KFn>(&k_potrf_large<NW, 0>);
+      case 1: return reinterpret_cast<KFn>(&k_potrf_large<NW, 1>);
+      case 2: return reinterpret_cast<KFn>(&k_potrf_large<NW, 2>);
     }
   } else if (op == TLA_TRSYL) {
     switch (var) {
-      case 0: return reinterpret_cast<KFn>(&k_trsyl_large<0>);
-      case 1: return reinterpret_cast<KFn>(&k_trsyl_large<1>);
-      case 2: return reinterpret_cast<KFn>(&k_trsyl_large<2>);
-      case 3: return reinterpret_cast<KFn>(&k_trsyl_large<3>);
-      case 4: return reinterpret_cast<KFn>(&k_trsyl_large<4>);
+      case 0: return reinterpret_cast<KFn>(&k_trsyl_large<NW, 0>);
+      case 1: return reinterpret_cast<KFn>(&k_trsyl_large<NW, 1>);
+      case 2: return reinterpret_cast<KFn>(&k_trsyl_large<NW, 2>);
+      case 3: return reinterpret_cast<KFn>(&k_trsyl_large<NW, 3>);
+      case 4: return reinterpret_cast<KFn>(&k_trsyl_large<NW, 4>);
     }
   } else if (op == TLA_TRLYAP) {
     switch (var) {
-      case 0: return reinterpret_cast<KFn>(&k_trlyap_large<0>);
-      case 1: return reinterpret_cast<KFn>(&k_trlyap_large<1>);
-      case 2: return reinterpret_cast<KFn>(&k_trlyap_large<2>);
+      case 0: return reinterpret_cast<KFn>(&k_trlyap_large<NW, 0>);
+      case 1: return reinterpret_cast<KFn>(&k_trlyap_large<NW, 1>);
+      case 2: return reinterpret_cast<KFn>(&k_trlyap_large<NW, 2>);
     }
   }
   return nullptr;
 }
 
-size_t large_lds_bytes() { return (size_t)kLargeNW * wave_scratch(kLargeTB) * sizeof(double) + 16; }
+KFn large_kernel(int op, int var) { return inplace_kernel_nw<kLargeNW>(op, var); }
+size_t large_lds_bytes() { return inplace_lds_bytes(kLargeNW); }
 int large_waves() { return kLargeNW; }
+
+KFn inplace_kernel(int op, int var, int nwi) {
+  switch (nwi) {
+    case 0: return inplace_kernel_nw<1>(op, var);
+    case 1: return inplace_kernel_nw<2>(op, var);
+    case 2: return inplace_kernel_nw<4>(op, var);
+  }
+  return nullptr;
+}
+size_t inplace_lds_bytes(int nw) { return (size_t)nw * wave_scratch(kLargeTB) * sizeof(double) + 16; }
 
 }  // namespace tla

@@ -21,7 +21,7 @@
 
 namespace tla {
 
-constexpr int kMlpIn = 24, kMlpH = 64;
+constexpr int kMlpIn = 25, kMlpH = 64;
 constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kMlpH * kMlpIn, kOffW2 = kOffB1 + kMlpH, kOffB2 = kOffW2 + kMlpH * kMlpH,
               kOffW3 = kOffB2 + kMlpH, kOffB3 = kOffW3 + kMlpH, kMlpParams = kOffB3 + 1;
 
@@ -41,7 +41,8 @@ struct MlpState {
 // ----------------------------------------------------------------- features
 // op one-hot (3), precision one-hot (4), n terms (4), batch (1), variant
 // one-hot (5), tile 16 (1), matrix cores (1), waves one-hot (3), tile count
-// squared (1), coefficients through the caches (1).
+// squared (1), coefficients through the caches (1), solved in place in global
+// memory (1).
 void mlp_features(int op, int n, int prec, int batch, const tla_plan& p, float* f) {
   for (int i = 0; i < kMlpIn; ++i) f[i] = 0.f;
   f[op] = 1.f;
@@ -57,7 +58,8 @@ void mlp_features(int op, int n, int prec, int batch, const tla_plan& p, float* 
   f[18] = p.engine ? 1.f : 0.f;
   f[19 + (p.waves == 1 ? 0 : (p.waves == 2 ? 1 : 2))] = 1.f;
   f[22] = f[10] * f[10];
-  f[23] = p.place ? 1.f : 0.f;
+  f[23] = (p.place == 1 || p.place == 2) ? 1.f : 0.f;
+  f[24] = p.place == 3 ? 1.f : 0.f;
 }
 
 // ------------------------------------------------------------------ kernels

@@ -29,9 +29,12 @@ KFn trlyap_mixed_kernel(int prec, int var, int te, int nwi, int placement);
 }  // namespace tla
 
 namespace tla {
-// Large sizes (n above the LDS-resident maximum): in-place kernels over
-// global memory, FP64, one per variant; 16 waves per instance.
+// In-place kernels over global memory, FP64, 16 x 16 matrix-core tiles.
+// Large sizes (n above the LDS-resident maximum): one per variant, 16 waves
+// per instance.  Placement 3 of the smaller sizes: nwi as above.
 KFn large_kernel(int op, int var);
 size_t large_lds_bytes();
 int large_waves();
+KFn inplace_kernel(int op, int var, int nwi);
+size_t inplace_lds_bytes(int nw);
 }  // namespace tla

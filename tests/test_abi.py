@@ -36,8 +36,12 @@ def test_host_only_queries():
     import paper_1906_08613_amd as tla
     if not os.path.exists(tla.LIB_PATH):
         pytest.skip("libtla.so not built")
-    assert tla.num_candidates("potrf") == 54      # 3 variants x 3 tile/engine x 3 waves x 2 placements
-    assert tla.num_candidates("trsyl") == 135     # 5 variants x 3 tile/engine x 3 waves x 3 placements
+    # variants x 3 tile/engine x 3 waves x LDS placements, plus variants x 3 waves in place (placement 3)
+    assert tla.num_candidates("potrf") == 54 + 9
+    assert tla.num_candidates("trsyl") == 135 + 15
+    assert tla.num_candidates("trlyap") == 81 + 9
+    p = tla.candidate("trsyl", 135 + 4)
+    assert (p.variant, p.tile, p.engine, p.waves, p.place) == (1, 16, 1, 2, 3)
     assert tla.variant_name("trsyl", 0) == "tile-wavefront"
     assert tla.lib().tla_status_string(4).decode() == "unsupported"
     # a null handle is rejected before any device work

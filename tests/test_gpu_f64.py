@@ -29,7 +29,8 @@ def h():
 
 
 def all_plans(op):
-    # place 2 (solution in the workspace) exists for the mixed kernels only
+    # place 2 (solution in the workspace) exists for the mixed kernels only;
+    # place 3 (in place in global memory) is an FP64 placement and included
     return [p for p in (tla.candidate(op, i).astuple() for i in range(tla.num_candidates(op))) if p[4] != 2]
 
 

@@ -195,6 +195,8 @@ def test_every_mixed_plan(h, orc, op):
     for prec in MIXED:
         for i in range(tla.num_candidates(op)):
             plan = tla.candidate(op, i).astuple()
+            if plan[4] == 3:  # in place in global memory: FP64 kernels only
+                continue
             print(f"{op} {prec} plan={plan}", flush=True)
             X, ops = solve(h, op, mats, prec, plan)
             assert eta_fn(*mats, X).max() <= 1e-12, (prec, plan)
