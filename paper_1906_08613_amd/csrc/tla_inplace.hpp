@@ -1,0 +1,133 @@
+// In-place solver bodies: the matrices stay in global memory and are solved
+// in place; only the tile solvers' scratch lives in LDS.  Tiles stream through
+// registers and the matrix cores (16 x 16 tiles), the same blocked variants as
+// for the LDS-resident kernels.  Used for the large sizes (n > 128, one
+// workgroup of 16 wavefronts per instance), as placement 3 of the smaller
+// sizes (1, 2 or 4 wavefronts: with no matrix in LDS many more instances are
+// resident per compute unit, and the caches serve the tile traffic) and by
+// the ragged workers.
+#pragma once
+#include "tla_kernels.hpp"
+
+namespace tla {
+
+// In/out view of the caller's matrix for in-place solves.  Reads outside
+// n x n return the padding (1 on the diagonal for the Cholesky pivots, 0
+// elsewhere) and writes there are dropped.  upper_only (Cholesky): the strict
+// lower triangle is neither read (reads return 0) nor written.
+template <class T>
+struct IOView {
+  double* p;
+  int ld, n;
+  bool upper_only;
+  int r0, c0;
+  bool tr;
+  TLA_DI void coords(int i, int j, int& r, int& c) const {
+    r = tr ? r0 + j : r0 + i;
+    c = tr ? c0 + i : c0 + j;
+  }
+  TLA_DI T operator()(int i, int j) const {
+    int r, c;
+    coords(i, j, r, c);
+    const bool in = r < n && c < n;
+    const int rr = r < n ? r : n - 1, cc = c < n ? c : n - 1;
+    const double raw = to_gbl(p)[rr + (size_t)cc * ld];
+    if (!in) return (upper_only && r == c) ? T(1) : T(0);
+    return (upper_only && r > c) ? T(0) : T(raw);
+  }
+  TLA_DI void store(int i, int j, T v) const {
+    int r, c;
+    coords(i, j, r, c);
+    if (r < n && c < n && !(upper_only && r > c)) to_gbl(p)[r + (size_t)c * ld] = double(v);
+  }
+  TLA_DI void fence() const { __threadfence_block(); }
+  TLA_DI IOView sub(int i0, int j0) const {
+    IOView v = *this;
+    if (tr) { v.r0 += j0; v.c0 += i0; } else { v.r0 += i0; v.c0 += j0; }
+    return v;
+  }
+  TLA_DI IOView t() const { IOView v = *this; v.tr = !tr; return v; }
+};
+
+template <class T>
+TLA_DI IOView<T> ioview(double* p, int ld, int n, bool upper_only) { return IOView<T>{p, ld, n, upper_only, 0, 0, false}; }
+
+constexpr int kLargeTB = 16, kLargeNW = 16;
+
+
+template <int NW>
+TLA_DI void large_ctx_init(unsigned char* smem, Ctx<double>& cx, int n, int*& s_info, int init) {
+  double* wb = reinterpret_cast<double*>(smem);
+  s_info = reinterpret_cast<int*>(wb + NW * wave_scratch(kLargeTB));
+  if (threadIdx.x == 0) *s_info = init;
+  __syncthreads();
+  cx = Ctx<double>{n, (n + kLargeTB - 1) / kLargeTB, to_lds(wb + wave_id() * wave_scratch(kLargeTB)), to_lds(s_info)};
+}
+
+template <int NW, int VAR>
+TLA_DI void potrf_inplace_body(const KArgs& g, const Inst& in, unsigned char* smem) {
+  int n;
+  if (skip_unflagged(g, in)) return;
+  if (!validate(in, g.n_max, n)) return;
+  Ctx<double> cx;
+  int* s_info;
+  large_ctx_init<NW>(smem, cx, n, s_info, 0);
+  potrf_blocked<double, kLargeTB, ENG_MFMA, NW, VAR>(ioview<double>(in.c, in.ldc, n, true), cx);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *in.info = *s_info;
+    if (in.stat && !g.only_flagged) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
+  }
+}
+
+template <int NW, int VAR>
+TLA_DI void trsyl_inplace_body(const KArgs& g, const Inst& in, unsigned char* smem) {
+  int n;
+  if (skip_unflagged(g, in)) return;
+  if (!validate(in, g.n_max, n)) return;
+  Ctx<double> cx;
+  int* s_info;
+  large_ctx_init<NW>(smem, cx, n, s_info, INT_MAX);
+  const GView<double> L = gview<double>(in.a, in.lda, n, -1);
+  const GView<double> U = gview<double>(in.b, in.ldb, n, +1);
+  scan_zero_denoms(L, U, n, false, s_info);
+  trsyl_blocked<double, kLargeTB, ENG_MFMA, NW, VAR>(ioview<double>(in.c, in.ldc, n, false), L, U, cx);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *in.info = *s_info == INT_MAX ? 0 : *s_info;
+    if (in.stat && !g.only_flagged) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
+  }
+}
+
+// mirrors the lower triangle of the caller's n x n matrix into its upper one
+template <int NW>
+TLA_DI void mirror_global(double* p, int ld, int n) {
+  gbl_t<double>* q = to_gbl(p);
+  for (int j = wave_id(); j < n; j += NW)
+    for (int i = lane_id(); i < j; i += 64) q[i + (size_t)j * ld] = q[j + (size_t)i * ld];
+}
+
+template <int NW, int VAR>
+TLA_DI void trlyap_inplace_body(const KArgs& g, const Inst& in, unsigned char* smem) {
+  int n;
+  if (skip_unflagged(g, in)) return;
+  if (!validate(in, g.n_max, n)) return;
+  Ctx<double> cx;
+  int* s_info;
+  large_ctx_init<NW>(smem, cx, n, s_info, INT_MAX);
+  const GView<double> L = gview<double>(in.a, in.lda, n, -1);
+  scan_zero_denoms(L, L, n, true, s_info);
+  // S is given by its lower triangle; the diagonal tiles are used in full
+  mirror_global<NW>(in.c, in.ldc, n);
+  __syncthreads();
+  trlyap_blocked<double, kLargeTB, ENG_MFMA, NW, VAR>(ioview<double>(in.c, in.ldc, n, false), L, cx);
+  __syncthreads();
+  mirror_global<NW>(in.c, in.ldc, n);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *in.info = *s_info == INT_MAX ? 0 : *s_info;
+    if (in.stat && !g.only_flagged) { in.stat->iters = 0; in.stat->flags = 0; in.stat->eta = 0.0; }
+  }
+}
+
+}  // namespace tla

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "tla_host.h"
+#include "tla_inplace.hpp"
 #include "tla_mixed.hpp"
 
 namespace tla {
@@ -137,10 +138,34 @@ struct RagVariants { int v[3]; };
 
 // MIXED: 0 = FP64 solve, 1 = FP32 + FP64 refinement.  PL: placement of the
 // Sylvester/Lyapunov operands (and, for the mixed kernels, PL == 2 puts the
-// FP64 solution of all three operations in the workspace).
+// FP64 solution of all three operations in the workspace; for FP64, PL == 3
+// solves all three in place in global memory).
 template <int TB, int ENG, int NW, int MIXED, int PL>
 __device__ void rag_run(const KArgs& g, const Inst& in, int op, const RagVariants& rv, unsigned char* smem) {
-  if constexpr (MIXED == 0) {
+  if constexpr (MIXED == 0 && PL == 3) {
+    static_assert(TB == 16 && ENG == ENG_MFMA, "in-place workers use 16 x 16 matrix-core tiles");
+    if (op == TLA_POTRF) {
+      switch (rv.v[0]) {
+        case 0: potrf_inplace_body<NW, 0>(g, in, smem); break;
+        case 1: potrf_inplace_body<NW, 1>(g, in, smem); break;
+        default: potrf_inplace_body<NW, 2>(g, in, smem); break;
+      }
+    } else if (op == TLA_TRSYL) {
+      switch (rv.v[1]) {
+        case 0: trsyl_inplace_body<NW, 0>(g, in, smem); break;
+        case 1: trsyl_inplace_body<NW, 1>(g, in, smem); break;
+        case 2: trsyl_inplace_body<NW, 2>(g, in, smem); break;
+        case 3: trsyl_inplace_body<NW, 3>(g, in, smem); break;
+        default: trsyl_inplace_body<NW, 4>(g, in, smem); break;
+      }
+    } else {
+      switch (rv.v[2]) {
+        case 0: trlyap_inplace_body<NW, 0>(g, in, smem); break;
+        case 1: trlyap_inplace_body<NW, 1>(g, in, smem); break;
+        default: trlyap_inplace_body<NW, 2>(g, in, smem); break;
+      }
+    }
+  } else if constexpr (MIXED == 0) {
     if (op == TLA_POTRF) {
       switch (rv.v[0]) {
         case 0: potrf_f64_body<TB, ENG, NW, 0>(g, in, smem); break;
@@ -219,11 +244,12 @@ struct RagClassCfg {
 };
 
 static RagClassCfg rag_cfg(int prec, int cls, bool second_pass) {
-  // FP64: class 0 keeps the coefficients in LDS; larger classes read them
-  // through the caches so that several instances share a compute unit.
+  // FP64: class 0 keeps the operands in LDS; the larger classes solve in
+  // place in global memory so that many instances share a compute unit.
   if (prec == TLA_F64 || second_pass) {
     if (cls == 0) return {2, 0, reinterpret_cast<RagFn>(&k_ragged<16, ENG_MFMA, 2, 0, 0>)};
-    return {4, 1, reinterpret_cast<RagFn>(&k_ragged<16, ENG_MFMA, 4, 0, 1>)};
+    if (cls == 1) return {1, 3, reinterpret_cast<RagFn>(&k_ragged<16, ENG_MFMA, 1, 0, 3>)};
+    return {2, 3, reinterpret_cast<RagFn>(&k_ragged<16, ENG_MFMA, 2, 0, 3>)};
   }
   if (cls == 0) return {2, 0, reinterpret_cast<RagFn>(&k_ragged<16, ENG_MFMA, 2, 1, 0>)};
   if (cls == 1) return {4, 1, reinterpret_cast<RagFn>(&k_ragged<16, ENG_MFMA, 4, 1, 1>)};
@@ -328,7 +354,7 @@ static tla_status rag_plan(tla_ctx* h, int prec, int batch, int n_max, tla_stat*
       const int eff_prec = pass == 1 ? TLA_F64 : prec;
       for (int op = 0; op < 3; ++op) {
         int pl = cfg.pl;
-        if (op == TLA_POTRF) pl = (eff_prec != TLA_F64 && cfg.pl == 2) ? 2 : 0;
+        if (op == TLA_POTRF && pl != 3) pl = (eff_prec != TLA_F64 && cfg.pl == 2) ? 2 : 0;
         L.lds = std::max(L.lds, lds_bytes(op, eff_prec, 16, cfg.waves, g.ntmax, pl));
       }
       if (L.lds > (size_t)h->lds_limit) return TLA_E_UNSUPPORTED;
