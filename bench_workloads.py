@@ -3,7 +3,8 @@ python bench.py --workload {potrf16,sweep,ragged,large,planner}.
 
 potrf16 : FP64 Cholesky, 1024 instances at n = 16, replayed many times inside
           one HIP graph (the batch is too small to fill the GPU by itself).
-sweep   : FP64 Sylvester and Lyapunov, n = 4, 8, ..., 128, 4096 instances each.
+sweep   : FP64 Sylvester and Lyapunov, n = 4, 8, ..., 128, 4096 instances each,
+          tuned plans.
 ragged  : 65536 mixed instances (40% Cholesky, 30% Sylvester, 30% Lyapunov),
           n uniform on {3..128}, FP64 and mixed, one graph-captured call.
 large   : 256 instances at n = 256, 512, 1024, FP64.
@@ -91,8 +92,11 @@ def sweep(a):
     from paper_1906_08613_amd import inputs as I
     h = tla.Handle(0)
     batch = 4096
+    sizes = list(range(4, 129, 4))
+    # the autotuner's plan for every size (outside the timed launches)
+    h.tune(["trsyl", "trlyap"], sizes, ["f64"], batch=batch, reps=2)
     for opname, op in (("trsyl", 1), ("trlyap", 2)):
-        for n in range(4, 129, 4):
+        for n in sizes:
             if op == 1:
                 L, U, C = I.trsyl_problem("cfg1", n, batch)
                 dL, dU, dC = tla.to_device_cm(L), tla.to_device_cm(U), tla.to_device_cm(C)

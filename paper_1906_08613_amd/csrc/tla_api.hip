@@ -72,15 +72,31 @@ bool candidate(int op, int i, tla_plan* p) {
   return true;
 }
 
+// The plan used without a tuning table: 16 x 16 matrix-core tiles, the
+// tile-wavefront / right-looking variant, and the placement that measured best
+// at n = 64 (FP64 above n = 32 in place in global memory, except Cholesky,
+// whose factor stays in LDS up to n = 64; mixed above n = 32 with the FP64
+// solution in the workspace).
 tla_plan default_plan(int op, int n, int prec) {
-  (void)prec;
   tla_plan p;
   p.variant = 0;
   p.tile = 16;
   p.engine = 1;
-  p.waves = n <= 16 ? 1 : (n <= 32 ? 2 : 4);
-  p.place = 0;
-  (void)op;
+  if (n <= 32) {
+    p.waves = n <= 16 ? 1 : 2;
+    p.place = 0;
+  } else if (prec == TLA_F64) {
+    if (op == TLA_POTRF && n <= 64) {
+      p.waves = 4;
+      p.place = 0;
+    } else {
+      p.waves = op == TLA_TRSYL ? 1 : 2;
+      p.place = 3;
+    }
+  } else {
+    p.waves = op == TLA_POTRF ? 4 : 2;
+    p.place = 2;
+  }
   return p;
 }
 
