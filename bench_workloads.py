@@ -7,7 +7,7 @@ sweep   : FP64 Sylvester and Lyapunov, n = 4, 8, ..., 128, 4096 instances each,
           tuned plans.
 ragged  : 65536 mixed instances (40% Cholesky, 30% Sylvester, 30% Lyapunov),
           n uniform on {3..128}, FP64 and mixed, one graph-captured call.
-large   : 256 instances at n = 256, 512, 1024, FP64.
+large   : 256 instances at n = 256, 512, 1024, FP64, tuned variants.
 planner : autotuner timings for n = 3..128 and the MLP trained on them;
           regret of the learned picker on held-out n against the measured best.
 All inputs are synthetic and seeded (paper_1906_08613_amd.inputs); results
@@ -218,6 +218,8 @@ def large(a):
     from paper_1906_08613_amd import inputs as I
     h = tla.Handle(0)
     batch = 256
+    # the autotuner's variant for every (op, n): at these sizes only the variant differs
+    h.tune(["potrf", "trsyl", "trlyap"], [256, 512, 1024], ["f64"], batch=batch, reps=2)
     for n in (256, 512, 1024):
         for opname, op in (("potrf", 0), ("trsyl", 1), ("trlyap", 2)):
             if op == 0:

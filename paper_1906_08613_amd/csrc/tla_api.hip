@@ -73,13 +73,14 @@ bool candidate(int op, int i, tla_plan* p) {
 }
 
 // The plan used without a tuning table: 16 x 16 matrix-core tiles, the
-// tile-wavefront / right-looking variant, and the placement that measured best
-// at n = 64 (FP64 above n = 32 in place in global memory, except Cholesky,
-// whose factor stays in LDS up to n = 64; mixed above n = 32 with the FP64
-// solution in the workspace).
+// tile-wavefront / right-looking variant (left-looking for the Cholesky
+// factorisation of the large sizes, where it measured 1.4x faster), and the
+// placement that measured best at n = 64 (FP64 above n = 32 in place in
+// global memory, except Cholesky, whose factor stays in LDS up to n = 64;
+// mixed above n = 32 with the FP64 solution in the workspace).
 tla_plan default_plan(int op, int n, int prec) {
   tla_plan p;
-  p.variant = 0;
+  p.variant = (op == TLA_POTRF && n > kMaxN) ? 1 : 0;
   p.tile = 16;
   p.engine = 1;
   if (n <= 32) {

@@ -165,9 +165,15 @@ extern "C" tla_status tla_tune(tla_handle h, int n_ops, const int* ops, int n_ns
         const int prec = precs[ip];
         double best = INFINITY;
         tla_plan bp{};
+        bool seen[8] = {false, false, false, false, false, false, false, false};
         for (int c = 0; c < num_candidates(op); ++c) {
           tla_plan p;
           candidate(op, c, &p);
+          // above the LDS-resident sizes only the variant selects a kernel
+          if (n > kMaxN) {
+            if (seen[p.variant]) continue;
+            seen[p.variant] = true;
+          }
           double sec = 0;
           st = time_plan(h, B, op, prec, p, reps, &sec);
           if (st == TLA_E_UNSUPPORTED) continue;
