@@ -45,8 +45,10 @@ def parse():
     p.add_argument("--cpu-sample", type=int, default=384)
     p.add_argument("--ops", default="potrf,trsyl,trlyap")
     p.add_argument("--workload", default="headline",
-                   choices=["headline", "potrf16", "sweep", "ragged", "large", "planner"],
+                   choices=["headline", "potrf16", "sweep", "ragged", "large", "planner", "plan"],
                    help="headline: the metric's configuration (default); the others print their own lines")
+    p.add_argument("--plan", default=None, metavar="V,T,E,W,P",
+                   help="--workload plan: time this plan (variant,tile,engine,waves,place) for the first of --ops")
     p.add_argument("--no-tune", action="store_true", help="skip autotuning the headline configuration first")
     p.add_argument("--table", default=None, help="load a tuning table instead of tuning")
     p.add_argument("--save-table", default=None, help="write the tuning table here")

@@ -10,6 +10,9 @@ ragged  : 65536 mixed instances (40% Cholesky, 30% Sylvester, 30% Lyapunov),
 large   : 256 instances at n = 256, 512, 1024, FP64, tuned variants.
 planner : autotuner timings for n = 3..128 and the MLP trained on them;
           regret of the learned picker on held-out n against the measured best.
+plan    : one operation (first of --ops) at --n, --batch, --prec with the plan
+          given by --plan, timed by the library's own timer (for profiling
+          one kernel).
 All inputs are synthetic and seeded (paper_1906_08613_amd.inputs); results
 are checked against the CPU oracle on a sample.
 """
@@ -313,5 +316,19 @@ def planner(a):
                       "regret_default_plan_mean": float(r_default.mean())}))
 
 
+def plan(a):
+    import torch  # noqa: F401  (device context for the library)
+    import paper_1906_08613_amd as tla
+    op = a.ops.split(",")[0]
+    p = tuple(int(x) for x in (a.plan or "0,16,1,4,0").split(","))
+    h = tla.Handle(0)
+    t = h.time_plan(op, a.n, a.prec, a.batch, p, reps=3)
+    fl = {"potrf": a.n ** 3 / 3.0}.get(op, 2.0 * a.n ** 3)
+    print(json.dumps({"workload": f"{op} {a.prec} n={a.n} x{a.batch} plan={list(p)}", "seconds": t,
+                      "solves_per_s": a.batch / t, "gflops": a.batch * fl / t / 1e9}))
+    h.close()
+
+
 def run(a):
-    {"potrf16": potrf16, "sweep": sweep, "ragged": ragged, "large": large, "planner": planner}[a.workload](a)
+    {"potrf16": potrf16, "sweep": sweep, "ragged": ragged, "large": large, "planner": planner,
+     "plan": plan}[a.workload](a)
