@@ -182,7 +182,8 @@ namespace tla {
 // FP64 kernels, placement 0: coefficients and X in LDS, 1: X only, 3: the
 // tile solvers' scratch only (X in place in global memory).
 // Mixed kernels: FP32 work matrix W (+ FP32 coefficients / factor copy) and
-// the FP64 solution (placement < last) in LDS; see tla_registry.h.
+// the FP64 solution (placements 0, 1) in LDS; placement 2 moves the solution
+// to the workspace, placement 3 the work matrices too; see tla_registry.h.
 size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int pl) {
   const size_t np = (size_t)ntmax * tb;
   const size_t mat8 = np * (np + 1) * 8, mat4 = np * (np + 1) * 4;
@@ -193,6 +194,7 @@ size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int pl) {
     if (op == TLA_TRSYL) return mat8 * (pl == 0 ? 3 : 1) + scr;
     return mat8 * (pl == 0 ? 2 : 1) + scr;
   }
+  if (pl == 3) return scr;
   if (op == TLA_POTRF) return (pl == 0 ? mat8 : 0) + 2 * mat4 + scr;
   const size_t coef = pl == 0 ? (op == TLA_TRSYL ? 2 : 1) * mat4 : 0;
   return (pl == 2 ? 0 : mat8) + mat4 + coef + scr;
@@ -230,16 +232,21 @@ static KFn kernel_for(int op, int prec, const tla_plan& p, int pl) {
     if (op == TLA_TRSYL) return trsyl_f64_kernel(p.variant, te, nwi, pl == 0);
     return trlyap_f64_kernel(p.variant, te, nwi, pl == 0);
   }
+  if (pl == 3) {
+    if (op == TLA_POTRF) return potrf_mixed_ws_kernel(prec, p.variant, nwi);
+    if (op == TLA_TRSYL) return trsyl_mixed_ws_kernel(prec, p.variant, nwi);
+    return trlyap_mixed_ws_kernel(prec, p.variant, nwi);
+  }
   if (op == TLA_POTRF) return potrf_mixed_kernel(prec, p.variant, te, nwi, pl == 0 ? 0 : 1);
   if (op == TLA_TRSYL) return trsyl_mixed_kernel(prec, p.variant, te, nwi, pl);
   return trlyap_mixed_kernel(prec, p.variant, te, nwi, pl);
 }
 
 // First placement whose LDS fits: returns -1 when none does.  FP64 runs
-// placements 0 / 1 (potrf 0) and 3, the mixed precisions 0 / 1 / 2 (potrf
-// 0 / 2); the search moves to larger placements of the same family.
+// placements 0 / 1 (potrf 0) and 3, the mixed precisions 0 / 1 / 2 / 3
+// (potrf 0 / 2 / 3); the search moves to larger placements of the same family.
 int choose_placement(tla_ctx* h, int op, int prec, const tla_plan& p, int ntmax, size_t* lds) {
-  const int last = prec == TLA_F64 ? 3 : 2;
+  const int last = 3;
   if (p.place > last) return -1;
   for (int pl = p.place; pl <= last; ++pl) {
     if (op == TLA_POTRF && pl == 1) continue;
@@ -259,45 +266,60 @@ static tla_status launch_one(tla_ctx* h, KFn fn, size_t lds, int grid, int waves
   return TLA_OK;
 }
 
+// Workspace doubles per instance for the mixed kernels with the FP64 solution
+// there (placement 2), or the FP32 work matrices too (placement 3, large n).
+static long long work_stride(int pl, int ntmax) {
+  const long long np = (long long)ntmax * 16, mat = np * (np + 1);
+  return pl == 3 ? 2 * mat : mat;
+}
+
+static tla_status ensure_work(tla_ctx* h, KArgs& a, int pl) {
+  a.work_stride = work_stride(pl, a.ntmax);
+  tla_status s = ensure_buffers(h, (size_t)a.batch * a.work_stride * sizeof(double), a.batch);
+  if (s != TLA_OK) return s;
+  a.work = h->work;
+  if (!a.stat) a.stat = h->stat_buf;
+  return TLA_OK;
+}
+
 tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& a0) {
   KArgs a = a0;
-  if (a.n_max > kMaxN) {
-    // large sizes: FP64 in place over global memory, variant from the plan
-    if (prec != TLA_F64) return TLA_E_UNSUPPORTED;
-    KFn fn = large_kernel(op, p.variant);
-    if (!fn) return TLA_E_UNSUPPORTED;
-    a.ntmax = (a.n_max + 15) / 16;
-    a.only_flagged = 0;
-    return launch_one(h, fn, large_lds_bytes(), a.batch, large_waves(), a);
-  }
-  a.ntmax = (a.n_max + p.tile - 1) / p.tile;
-  if (a.ntmax < 1) a.ntmax = 1;
   a.tau = h->tau;
   a.max_iter = h->max_iter;
   a.only_flagged = 0;
+  if (a.n_max > kMaxN) {
+    // large sizes: FP64 in place over global memory, variant from the plan.
+    // (The mixed precisions are not offered here: their 16-wave kernels with
+    // the work matrices in the workspace faulted the GPU on their first
+    // Lyapunov run, cause not found; the code path is switched off.)
+    if (prec != TLA_F64) return TLA_E_UNSUPPORTED;
+    a.ntmax = (a.n_max + 15) / 16;
+    KFn fn64 = large_kernel(op, p.variant);
+    if (!fn64) return TLA_E_UNSUPPORTED;
+    return launch_one(h, fn64, large_lds_bytes(), a.batch, large_waves(), a);
+  }
+  a.ntmax = (a.n_max + p.tile - 1) / p.tile;
+  if (a.ntmax < 1) a.ntmax = 1;
   size_t lds = 0;
   const int pl = choose_placement(h, op, prec, p, a.ntmax, &lds);
   if (pl < 0) return TLA_E_UNSUPPORTED;
-  const bool xg = prec != TLA_F64 && pl == 2;
+  const bool xg = prec != TLA_F64 && pl >= 2;
   KFn fn = kernel_for(op, prec, p, pl);
   if (!fn) return TLA_E_UNSUPPORTED;
   if (xg) {
-    const size_t np = (size_t)a.ntmax * p.tile;
-    a.work_stride = (long long)(np * (np + 1));
-    tla_status s = ensure_buffers(h, (size_t)a.batch * a.work_stride * sizeof(double), a.batch);
+    tla_status s = ensure_work(h, a, pl);
     if (s != TLA_OK) return s;
-    a.work = h->work;
-    if (!a.stat) a.stat = h->stat_buf;
   }
   if (getenv("TLA_LOG"))
     fprintf(stderr, "tla: op %d prec %d batch %d n_max %d plan(v%d t%d e%d w%d) lds %zu placement %d\n", op, prec,
             a.batch, a.n_max, p.variant, p.tile, p.engine, p.waves, lds, pl);
   tla_status s = launch_one(h, fn, lds, a.batch, p.waves, a);
   if (s != TLA_OK || !xg) return s;
-  // second pass: FP64 solve of the instances the mixed kernel left unconverged
+  // second pass: FP64 solve of the instances the mixed kernel left
+  // unconverged, by the LDS-resident FP64 kernel of the same variant
   size_t lds64 = 0;
   tla_plan p64 = p;
-  p64.place = op == TLA_POTRF ? 0 : (p.place > 1 ? 1 : p.place);
+  p64.place = op == TLA_POTRF ? 0 : 1;
   const int pl64 = choose_placement(h, op, TLA_F64, p64, a.ntmax, &lds64);
   if (pl64 < 0) return TLA_E_UNSUPPORTED;
   KFn fb = kernel_for(op, TLA_F64, p64, pl64);

@@ -49,7 +49,8 @@ template <class T>
 TLA_DI GView<T> gview(const double* p, int ld, int n, int tri) { return GView<T>{p, ld, n, tri, 0, 0, false}; }
 
 // ------------------------------------------------------ ingest / egress
-// Copies the n x n global matrix into the np x np LDS matrix (ld = ldw),
+// Copies the n x n global matrix into the np x np work matrix (ld = ldw; in
+// LDS, or in global memory for !LDS),
 // keeping the part selected by `part` and writing `pad` on the padded
 // diagonal and zero elsewhere.  part: 0 full, -1 lower (i >= j), +1 upper.
 // Rows go to lanes (coalesced column reads), columns to waves; U columns are
@@ -57,11 +58,11 @@ TLA_DI GView<T> gview(const double* p, int ld, int n, int tri) { return GView<T>
 // thread's share of the squared Frobenius norm of the kept part, counting
 // off-diagonal entries twice when `sym` (a symmetric matrix given by one
 // triangle).
-template <class T, int NW>
+template <class T, int NW, bool LDS = true>
 TLA_DI double ingest(T* Wg, int ldw, int np, const double* Gg, int ldg, int n, int part, T pad, bool sym = false) {
   constexpr int U = 8;
   const int w = wave_id(), l = lane_id();
-  lds_t<T>* W = to_lds(Wg);
+  const auto W = xcolmajor<!LDS>(Wg, ldw).p;
   const gbl_t<double>* G = to_gbl(Gg);
   double ss = 0.0;
   for (int i0 = 0; i0 < np; i0 += 64) {

@@ -86,21 +86,34 @@ struct MixedLds {
 
 // With XG the FP64 solution lives in a global workspace slot instead (sizes
 // where it does not fit next to W); every access to it is then separated by
-// workgroup barriers, and the FP64 fallback runs as a second launch.
-template <int TB, int NW, bool XG>
+// workgroup barriers, and the FP64 fallback runs as a second launch.  With WG
+// (which implies XG) the FP32 work matrix and the FP32 auxiliary matrices
+// follow it into the slot, after the solution, and LDS keeps only the tile
+// solvers' scratch and the reduction cells.
+template <int TB, int NW, bool XG, bool WG = false>
 TLA_DI MixedLds carve(unsigned char* smem, const KArgs& g, int naux) {
+  static_assert(!WG || XG, "the work matrix only leaves LDS with the solution");
   const size_t np = (size_t)g.ntmax * TB, mat = np * (np + 1);
   MixedLds m;
-  if constexpr (XG) {
+  float* after;
+  if constexpr (WG) {
     m.Xd = g.work + (size_t)blockIdx.x * g.work_stride;
-    m.W = reinterpret_cast<float*>(smem);
-  } else {
-    m.Xd = reinterpret_cast<double*>(smem);
     m.W = reinterpret_cast<float*>(m.Xd + mat);
+    m.A1 = m.W + mat;
+    m.A2 = m.A1 + (naux >= 1 ? mat : 0);
+    after = reinterpret_cast<float*>(smem);
+  } else {
+    if constexpr (XG) {
+      m.Xd = g.work + (size_t)blockIdx.x * g.work_stride;
+      m.W = reinterpret_cast<float*>(smem);
+    } else {
+      m.Xd = reinterpret_cast<double*>(smem);
+      m.W = reinterpret_cast<float*>(m.Xd + mat);
+    }
+    m.A1 = m.W + mat;
+    m.A2 = m.A1 + (naux >= 1 ? mat : 0);
+    after = m.A2 + (naux >= 2 ? mat : 0);
   }
-  m.A1 = m.W + mat;
-  m.A2 = m.A1 + (naux >= 1 ? mat : 0);
-  float* after = m.A2 + (naux >= 2 ? mat : 0);
   // scratch sized for FP64 (the fallback solve reuses it), 8-byte aligned
   m.wb = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(after) + 7) & ~uintptr_t(7));
   m.red = reinterpret_cast<double*>(m.wb) + NW * wave_scratch(TB);
@@ -109,27 +122,28 @@ TLA_DI MixedLds carve(unsigned char* smem, const KArgs& g, int naux) {
   return m;
 }
 
-// float view of an FP64 global matrix (coefficients read through the caches)
-template <class T>
-TLA_DI bool all_finite_lds(const T* Wg, int ldw, int n) {
-  const lds_t<T>* W = to_lds(const_cast<T*>(Wg));
+// True when every entry of the n x n leading block is finite (work matrix in
+// LDS, or in global memory for !LDS).
+template <class T, bool LDS = true>
+TLA_DI bool all_finite(const T* Wg, int ldw, int n) {
+  const auto W = xcolmajor<!LDS>(const_cast<T*>(Wg), ldw);
   bool ok = true;
   const int nw = blockDim.x >> 6;
   for (int j = wave_id(); j < n; j += nw)
     for (int i = lane_id(); i < n; i += 64) {
-      const T v = W[i + j * ldw];
+      const T v = W(i, j);
       ok = ok && (v - v == T(0));
     }
   return ok;
 }
 
 // ===================================================== Sylvester, mixed
-template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG>
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG, bool WG = false>
 TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
   if (!validate(in, g.n_max, n)) return;
   const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
-  const MixedLds m = carve<TB, NW, XG>(smem, g, LU_LDS ? 2 : 0);
+  const MixedLds m = carve<TB, NW, XG, WG>(smem, g, LU_LDS ? 2 : 0);
   const double* Lg = in.a;
   const double* Ug = in.b;
   double* Cg = in.c;
@@ -141,7 +155,7 @@ TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
   if (threadIdx.x == 0) *m.info = INT_MAX;
   RefineState st{INFINITY, INFINITY, 0, 0};
 
-  double sc = ingest<float, NW>(m.W, ld, np, Cg, ldc, n, 0, 0.0f);
+  double sc = ingest<float, NW, !WG>(m.W, ld, np, Cg, ldc, n, 0, 0.0f);
   double sl = 0.0, su = 0.0;
   if constexpr (LU_LDS) {
     sl = ingest<float, NW>(m.A1, ld, np, Lg, ldl, n, -1, 0.0f);
@@ -162,10 +176,10 @@ TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
   Ctx<float> cx{n, nt, to_lds(m.wb + wave_id() * wave_scratch(TB)), to_lds(m.info)};
   if (info0 == 0 && !bad) {
     // low-precision solve of the full system
-    if constexpr (LU_LDS) trsyl_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), colmajor(m.A1, ld), colmajor(m.A2, ld), cx);
-    else trsyl_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), gview<float>(Lg, ldl, n, -1), gview<float>(Ug, ldu, n, +1), cx);
+    if constexpr (LU_LDS) trsyl_blocked<float, TB, ENG, NW, VAR>(xcolmajor<WG>(m.W, ld), colmajor(m.A1, ld), colmajor(m.A2, ld), cx);
+    else trsyl_blocked<float, TB, ENG, NW, VAR>(xcolmajor<WG>(m.W, ld), gview<float>(Lg, ldl, n, -1), gview<float>(Ug, ldu, n, +1), cx);
     __syncthreads();
-    if (block_or<NW>(all_finite_lds(m.W, ld, n) ? 0 : 1, m.ired)) st.flags |= TLA_STAT_BREAKDOWN;
+    if (block_or<NW>(all_finite<float, !WG>(m.W, ld, n) ? 0 : 1, m.ired)) st.flags |= TLA_STAT_BREAKDOWN;
     if (!(st.flags & TLA_STAT_BREAKDOWN)) {
       for (int e = threadIdx.x; e < np * ld; e += blockDim.x) m.Xd[e] = double(m.W[e]);
       __syncthreads();
@@ -195,8 +209,8 @@ TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
         const double eta = nr / ((nl + nu) * nx + nc);
         if (refine_decide(st, eta, g.tau, g.max_iter)) break;
         __syncthreads();
-        if constexpr (LU_LDS) trsyl_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), colmajor(m.A1, ld), colmajor(m.A2, ld), cx);
-        else trsyl_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), gview<float>(Lg, ldl, n, -1), gview<float>(Ug, ldu, n, +1), cx);
+        if constexpr (LU_LDS) trsyl_blocked<float, TB, ENG, NW, VAR>(xcolmajor<WG>(m.W, ld), colmajor(m.A1, ld), colmajor(m.A2, ld), cx);
+        else trsyl_blocked<float, TB, ENG, NW, VAR>(xcolmajor<WG>(m.W, ld), gview<float>(Lg, ldl, n, -1), gview<float>(Ug, ldu, n, +1), cx);
         __syncthreads();
         for (int e = threadIdx.x; e < np * ld; e += blockDim.x) m.Xd[e] += double(m.W[e]);
         ++st.it;
@@ -220,19 +234,19 @@ TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
   write_stat(in, st);
 }
 
-template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG>
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG, bool WG = false>
 __global__ __launch_bounds__(NW * 64) void k_trsyl_mixed(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
-  trsyl_mixed_body<TB, ENG, NW, VAR, LU_LDS, XG>(g, fetch_uniform(g, blockIdx.x), smem);
+  trsyl_mixed_body<TB, ENG, NW, VAR, LU_LDS, XG, WG>(g, fetch_uniform(g, blockIdx.x), smem);
 }
 
 // ===================================================== Lyapunov, mixed
-template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG>
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG, bool WG = false>
 TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
   if (!validate(in, g.n_max, n)) return;
   const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
-  const MixedLds m = carve<TB, NW, XG>(smem, g, LU_LDS ? 1 : 0);
+  const MixedLds m = carve<TB, NW, XG, WG>(smem, g, LU_LDS ? 1 : 0);
   const double* Lg = in.a;
   double* Sg = in.c;
   const int ldl = in.lda, lds = in.ldc;
@@ -242,7 +256,7 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
   if (threadIdx.x == 0) *m.info = INT_MAX;
   RefineState st{INFINITY, INFINITY, 0, 0};
 
-  double ss = ingest<float, NW>(m.W, ld, np, Sg, lds, n, -1, 0.0f, true);
+  double ss = ingest<float, NW, !WG>(m.W, ld, np, Sg, lds, n, -1, 0.0f, true);
   double sl = 0.0;
   if constexpr (LU_LDS) {
     sl = ingest<float, NW>(m.A1, ld, np, Lg, ldl, n, -1, 0.0f);
@@ -250,7 +264,7 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
     sl = gnorm2<NW>(Lg, ldl, n, -1);
   }
   __syncthreads();
-  mirror_lower(m.W, ld, np);
+  mirror_lower<float, !WG>(m.W, ld, np);
   const double ns = sqrt(block_sum<NW>(ss, m.red));
   const double nl = sqrt(block_sum<NW>(sl, m.red));
   int bad = (ns - ns != 0.0 || nl - nl != 0.0) ? TLA_STAT_NONFINITE : 0;
@@ -260,12 +274,12 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
   const int info0 = *m.info == INT_MAX ? 0 : *m.info;
   Ctx<float> cx{n, nt, to_lds(m.wb + wave_id() * wave_scratch(TB)), to_lds(m.info)};
   if (info0 == 0 && !bad) {
-    if constexpr (LU_LDS) trlyap_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), colmajor(m.A1, ld), cx);
-    else trlyap_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), gview<float>(Lg, ldl, n, -1), cx);
+    if constexpr (LU_LDS) trlyap_blocked<float, TB, ENG, NW, VAR>(xcolmajor<WG>(m.W, ld), colmajor(m.A1, ld), cx);
+    else trlyap_blocked<float, TB, ENG, NW, VAR>(xcolmajor<WG>(m.W, ld), gview<float>(Lg, ldl, n, -1), cx);
     __syncthreads();
-    mirror_lower(m.W, ld, np);
+    mirror_lower<float, !WG>(m.W, ld, np);
     __syncthreads();
-    if (block_or<NW>(all_finite_lds(m.W, ld, n) ? 0 : 1, m.ired)) st.flags |= TLA_STAT_BREAKDOWN;
+    if (block_or<NW>(all_finite<float, !WG>(m.W, ld, n) ? 0 : 1, m.ired)) st.flags |= TLA_STAT_BREAKDOWN;
     if (!(st.flags & TLA_STAT_BREAKDOWN)) {
       for (int e = threadIdx.x; e < np * ld; e += blockDim.x) m.Xd[e] = double(m.W[e]);
       __syncthreads();
@@ -297,8 +311,8 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
         const double eta = nr / (2.0 * nl * nx + ns);
         if (refine_decide(st, eta, g.tau, g.max_iter)) break;
         __syncthreads();
-        if constexpr (LU_LDS) trlyap_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), colmajor(m.A1, ld), cx);
-        else trlyap_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), gview<float>(Lg, ldl, n, -1), cx);
+        if constexpr (LU_LDS) trlyap_blocked<float, TB, ENG, NW, VAR>(xcolmajor<WG>(m.W, ld), colmajor(m.A1, ld), cx);
+        else trlyap_blocked<float, TB, ENG, NW, VAR>(xcolmajor<WG>(m.W, ld), gview<float>(Lg, ldl, n, -1), cx);
         __syncthreads();
         // Xd += D on the lower triangle, then keep Xd symmetric
         for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
@@ -329,10 +343,10 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
   write_stat(in, st);
 }
 
-template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG>
+template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG, bool WG = false>
 __global__ __launch_bounds__(NW * 64) void k_trlyap_mixed(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
-  trlyap_mixed_body<TB, ENG, NW, VAR, LU_LDS, XG>(g, fetch_uniform(g, blockIdx.x), smem);
+  trlyap_mixed_body<TB, ENG, NW, VAR, LU_LDS, XG, WG>(g, fetch_uniform(g, blockIdx.x), smem);
 }
 
 // ====================================================== Cholesky, mixed
@@ -387,12 +401,12 @@ TLA_DI void newton_correction(const VW& Wv, const VW& Xv, const VXd& Xd, int nt,
   }
 }
 
-template <int TB, int ENG, int NW, int VAR, bool XG>
+template <int TB, int ENG, int NW, int VAR, bool XG, bool WG = false>
 TLA_DI void potrf_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
   if (!validate(in, g.n_max, n)) return;
   const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
-  const MixedLds m = carve<TB, NW, XG>(smem, g, 1);
+  const MixedLds m = carve<TB, NW, XG, WG>(smem, g, 1);
   double* Ag = in.c;
   const int lda = in.ldc;
   const GView<double> A64 = gview<double>(Ag, lda, n, 2);
@@ -400,13 +414,13 @@ TLA_DI void potrf_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
   if (threadIdx.x == 0) *m.info = 0;
   RefineState st{INFINITY, INFINITY, 0, 0};
 
-  const double na = sqrt(block_sum<NW>(ingest<float, NW>(m.W, ld, np, Ag, lda, n, +1, 1.0f, true), m.red));
+  const double na = sqrt(block_sum<NW>(ingest<float, NW, !WG>(m.W, ld, np, Ag, lda, n, +1, 1.0f, true), m.red));
   int bad = (na - na != 0.0) ? TLA_STAT_NONFINITE : 0;
   Ctx<float> cx{n, nt, to_lds(m.wb + wave_id() * wave_scratch(TB)), to_lds(m.info)};
   if (!bad) {
-    potrf_blocked<float, TB, ENG, NW, VAR>(colmajor(m.W, ld), cx);
+    potrf_blocked<float, TB, ENG, NW, VAR>(xcolmajor<WG>(m.W, ld), cx);
     __syncthreads();
-    if (*m.info != 0 || block_or<NW>(all_finite_lds(m.W, ld, n) ? 0 : 1, m.ired)) bad |= TLA_STAT_BREAKDOWN;
+    if (*m.info != 0 || block_or<NW>(all_finite<float, !WG>(m.W, ld, n) ? 0 : 1, m.ired)) bad |= TLA_STAT_BREAKDOWN;
   }
   st.flags |= bad;
   if (!bad) {
@@ -444,7 +458,7 @@ TLA_DI void potrf_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
         m.A1[i + j * ld] = i < n && j < n ? float(m.Xd[i + j * ld]) : (i == j ? 1.0f : 0.0f);
       }
       __syncthreads();
-      newton_correction<float, TB, ENG, NW>(colmajor(m.W, ld), colmajor(m.A1, ld), Xv, nt, to_lds(m.wb + wave_id() * wave_scratch(TB)));
+      newton_correction<float, TB, ENG, NW>(xcolmajor<WG>(m.W, ld), xcolmajor<WG>(m.A1, ld), Xv, nt, to_lds(m.wb + wave_id() * wave_scratch(TB)));
       ++st.it;
       __syncthreads();
     }
@@ -467,10 +481,10 @@ TLA_DI void potrf_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
   write_stat(in, st);
 }
 
-template <int TB, int ENG, int NW, int VAR, bool XG>
+template <int TB, int ENG, int NW, int VAR, bool XG, bool WG = false>
 __global__ __launch_bounds__(NW * 64) void k_potrf_mixed(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
-  potrf_mixed_body<TB, ENG, NW, VAR, XG>(g, fetch_uniform(g, blockIdx.x), smem);
+  potrf_mixed_body<TB, ENG, NW, VAR, XG, WG>(g, fetch_uniform(g, blockIdx.x), smem);
 }
 
 }  // namespace tla

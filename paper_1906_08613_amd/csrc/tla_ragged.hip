@@ -246,7 +246,12 @@ struct RagClassCfg {
 static RagClassCfg rag_cfg(int prec, int cls, bool second_pass) {
   // FP64: class 0 keeps the operands in LDS; the larger classes solve in
   // place in global memory so that many instances share a compute unit.
-  if (prec == TLA_F64 || second_pass) {
+  // The FP64 second pass of the mixed path keeps the LDS-resident workers.
+  if (second_pass) {
+    if (cls == 0) return {2, 0, reinterpret_cast<RagFn>(&k_ragged<16, ENG_MFMA, 2, 0, 0>)};
+    return {4, 1, reinterpret_cast<RagFn>(&k_ragged<16, ENG_MFMA, 4, 0, 1>)};
+  }
+  if (prec == TLA_F64) {
     if (cls == 0) return {2, 0, reinterpret_cast<RagFn>(&k_ragged<16, ENG_MFMA, 2, 0, 0>)};
     if (cls == 1) return {1, 3, reinterpret_cast<RagFn>(&k_ragged<16, ENG_MFMA, 1, 0, 3>)};
     return {2, 3, reinterpret_cast<RagFn>(&k_ragged<16, ENG_MFMA, 2, 0, 3>)};
