@@ -64,6 +64,8 @@ def lib():
             "orc_eta_trsyl": (c_double, [c_int, D, c_int, D, c_int, D, c_int, D, c_int]),
             "orc_eta_trlyap": (c_double, [c_int, D, c_int, D, c_int, D, c_int]),
             "orc_potrf_batch": (None, [c_int, c_int, D, D, I, c_int]),
+            "orc_potrs": (c_int, [c_int, c_int, D, c_int, D, c_int]),
+            "orc_potrs_batch": (None, [c_int, c_int, c_int, D, D, I, c_int]),
             "orc_trsyl_batch": (None, [c_int, c_int, D, D, D, D, I, c_int]),
             "orc_trlyap_batch": (None, [c_int, c_int, D, D, D, I, c_int]),
             "orc_eta_potrf_batch": (None, [c_int, c_int, D, D, D, c_int]),
@@ -110,6 +112,15 @@ def potrf(A):
     x = np.zeros_like(a)
     info = lib().orc_potrf(n, _dp(a), n, _dp(x), n)
     return _from_cm(x), info
+
+
+def potrs(X, B):
+    """A^{-1} B for A = X^T X, from the upper triangle of the factor X; B is (n, m) -> (Y, info)."""
+    n, m = B.shape
+    x = _cm(X)
+    y = _cm(B).copy()   # the solve overwrites it; never the caller's array
+    info = lib().orc_potrs(n, m, _dp(x), n, _dp(y), n)
+    return _from_cm(y), info
 
 
 def trsyl(L, U, C):
@@ -199,6 +210,16 @@ def potrf_batch(A, threads=0):
     info = np.zeros(b, dtype=np.int32)
     lib().orc_potrf_batch(b, n, _dp(a), _dp(x), _ip(info), threads)
     return _from_cm(x), info
+
+
+def potrs_batch(X, B, threads=0):
+    """Batched potrs: X (batch, n, n) upper factors, B (batch, n, m) -> (Y, info)."""
+    b, n, m = B.shape
+    x = _cm(X)
+    y = _cm(B).copy()   # the solve overwrites it; never the caller's array
+    info = np.zeros(b, dtype=np.int32)
+    lib().orc_potrs_batch(b, n, m, _dp(x), _dp(y), _ip(info), threads)
+    return _from_cm(y), info
 
 
 def trsyl_batch(L, U, C, threads=0):

@@ -58,6 +58,35 @@ int orc_potrf(int n, const double *A, int lda, double *X, int ldx) {
 }
 
 /*
+ * Solve with the upper Cholesky factor: the consumer of Fig. 2a that the
+ * paper's motivation names next to the factorizations (LAPACK solvers).
+ * Given X upper triangular with X^T X = A, overwrite the n x m right-hand
+ * sides B with A^{-1} B: forward substitution with X^T, then back
+ * substitution with X, column by column:
+ *   z_ij = (b_ij - sum_{k<i} x_ki z_kj) / x_ii         (i = 0 .. n-1)
+ *   y_ij = (z_ij - sum_{k>i} x_ik y_kj) / x_ii         (i = n-1 .. 0)
+ * Reads only the upper triangle of X.  Returns 0, or k > 0 when x_kk
+ * (1-based) is zero; B is then left unchanged.
+ */
+int orc_potrs(int n, int m, const double *X, int ldx, double *B, int ldb) {
+  for (int k = 0; k < n; ++k)
+    if (E(X, ldx, k, k) == 0.0) return k + 1;
+  for (int j = 0; j < m; ++j) {
+    for (int i = 0; i < n; ++i) {
+      double s = E(B, ldb, i, j);
+      for (int k = 0; k < i; ++k) s -= E(X, ldx, k, i) * E(B, ldb, k, j);
+      E(B, ldb, i, j) = s / E(X, ldx, i, i);
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = E(B, ldb, i, j);
+      for (int k = i + 1; k < n; ++k) s -= E(X, ldx, i, k) * E(B, ldb, k, j);
+      E(B, ldb, i, j) = s / E(X, ldx, i, i);
+    }
+  }
+  return 0;
+}
+
+/*
  * Triangular Sylvester L X + X U = C (Fig. 2c).  Reads the lower triangle of
  * L and the upper triangle of U.  Column by column, top to bottom:
  *   x_ij = (c_ij - sum_{k<i} l_ik x_kj - sum_{k<j} x_ik u_kj) / (l_ii + u_jj)
@@ -290,6 +319,13 @@ void orc_trlyap_batch(int batch, int n, const double *L, const double *S, double
 #pragma omp parallel for schedule(dynamic, 4)
   for (int b = 0; b < batch; ++b)
     info[b] = orc_trlyap(n, L + b * st, n, S + b * st, n, X + b * st, n);
+}
+
+void orc_potrs_batch(int batch, int n, int m, const double *X, double *B, int *info, int threads) {
+  set_threads(threads);
+  size_t sx = (size_t)n * n, sb = (size_t)n * m;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int b = 0; b < batch; ++b) info[b] = orc_potrs(n, m, X + b * sx, n, B + b * sb, n);
 }
 
 void orc_eta_potrf_batch(int batch, int n, const double *A, const double *X, double *eta, int threads) {
