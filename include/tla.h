@@ -118,6 +118,25 @@ tla_status tla_trlyap_batched(tla_handle h, tla_prec prec, int batch, int n_max,
                               const int *n, const double *const *L, const int *ldl,
                               double *const *S, const int *lds, int *info, tla_stat *stat);
 
+/* Solve with the upper Cholesky factor, FP64: for every instance b,
+ * B_b := (X_b^T X_b)^{-1} B_b by forward substitution with X_b^T and back
+ * substitution with X_b.  This is the consumer of the factorization
+ * (Fig. 2a) that the paper's motivation lists next to it among the LAPACK
+ * building blocks.
+ *   X[b]: the n[b] x n[b] upper factor as returned by tla_potrf_batched,
+ *         column-major with leading dimension ldx[b]; only its upper
+ *         triangle is read.
+ *   B[b]: n[b] x nrhs[b] right-hand sides, column-major with leading
+ *         dimension ldb[b]; overwritten with the solution.
+ *   0 <= n[b] <= n_max, 0 <= nrhs[b] <= nrhs_max.  All arrays (pointer
+ *   arrays included) are device memory owned by the caller.
+ * info[b]: 0; -1 bad n or nrhs; -2 ldx or ldb < max(1, n); k > 0 when the
+ * factor's diagonal entry x_kk (1-based) is zero, B_b then left unchanged.
+ * Asynchronous on the handle's stream. */
+tla_status tla_potrs_batched(tla_handle h, int batch, int n_max, const int *n, int nrhs_max, const int *nrhs,
+                             const double *const *X, const int *ldx, double *const *B, const int *ldb,
+                             int *info);
+
 /* Mixed batch of all three operations and uneven n in one persistent launch
  * (captured as a HIP graph and replayed when the same descriptor array, batch
  * and precision come again).  d: tla_desc[batch]. */

@@ -32,7 +32,7 @@ OPS = {"potrf": POTRF, "trsyl": TRSYL, "trlyap": TRLYAP}
 SYMBOLS = [
     "tla_create", "tla_destroy", "tla_set_stream", "tla_sync",
     "tla_potrf_batched", "tla_trsyl_batched", "tla_trlyap_batched", "tla_ragged_batched",
-    "tla_set_plan", "tla_get_plan", "tla_num_candidates", "tla_candidate", "tla_variant_name",
+    "tla_potrs_batched", "tla_set_plan", "tla_get_plan", "tla_num_candidates", "tla_candidate", "tla_variant_name",
     "tla_tune", "tla_time_plan", "tla_save_table", "tla_load_table", "tla_set_picker",
     "tla_set_refine", "tla_status_string",
     "tla_mlp_num_params", "tla_mlp_num_features", "tla_mlp_features", "tla_mlp_set_params",
@@ -90,6 +90,7 @@ def lib():
             "tla_trsyl_batched": (I, [V, I, I, I, P, P, P, P, P, P, P, P, P]),
             "tla_trlyap_batched": (I, [V, I, I, I, P, P, P, P, P, P, P]),
             "tla_ragged_batched": (I, [V, I, I, I, P, P, P]),
+            "tla_potrs_batched": (I, [V, I, I, P, I, P, P, P, P, P, P]),
             "tla_set_plan": (I, [V, I, I, ctypes.POINTER(Plan)]),
             "tla_get_plan": (I, [V, I, I, I, I, ctypes.POINTER(Plan)]),
             "tla_num_candidates": (I, [I]),
@@ -181,6 +182,10 @@ class Handle:
     def trlyap_batched(self, prec, batch, n_max, n, L, ldl, S, lds, info, stat=None):
         check(lib().tla_trlyap_batched(self.h, _prec(prec), batch, n_max, _ptr(n), _ptr(L), _ptr(ldl),
                                        _ptr(S), _ptr(lds), _ptr(info), _ptr(stat)), "tla_trlyap_batched")
+
+    def potrs_batched(self, batch, n_max, n, nrhs_max, nrhs, X, ldx, B, ldb, info):
+        check(lib().tla_potrs_batched(self.h, batch, n_max, _ptr(n), nrhs_max, _ptr(nrhs), _ptr(X), _ptr(ldx),
+                                      _ptr(B), _ptr(ldb), _ptr(info)), "tla_potrs_batched")
 
     def ragged_batched(self, prec, batch, n_max, desc, info, stat=None):
         check(lib().tla_ragged_batched(self.h, _prec(prec), batch, n_max, _ptr(desc), _ptr(info), _ptr(stat)),
@@ -322,6 +327,23 @@ def from_device_cm(t, n=None):
     return np.ascontiguousarray(np.swapaxes(a[:, :n, :n], 1, 2))
 
 
+def to_device_rect(M, device="cuda", ld=None):
+    """numpy (batch, n, m) indexed [b, i, j] -> column-major batch tensor (batch, m, ld)."""
+    import torch
+    M = np.asarray(M, dtype=np.float64)
+    b, n, m = M.shape
+    ld = ld or n
+    host = np.zeros((b, m, ld), dtype=np.float64)
+    host[:, :, :n] = np.swapaxes(M, 1, 2)
+    return torch.from_numpy(host).to(device)
+
+
+def from_device_rect(t, n):
+    """column-major batch tensor (batch, m, ld) -> numpy (batch, n, m) indexed [b, i, j]."""
+    a = t.detach().cpu().numpy()
+    return np.ascontiguousarray(np.swapaxes(a[:, :, :n], 1, 2))
+
+
 class Operands:
     """Device arrays describing one uniform batch: per-instance n and ld
     (int32) and pointer arrays (int64 device addresses) for each matrix."""
@@ -368,6 +390,18 @@ def trlyap(h: Handle, L, S, prec="f64", ops: Operands | None = None):
     h.trlyap_batched(prec, ops.batch, ops.n_max, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1],
                      ops.info, ops.stat)
     return ops
+
+
+def potrs(h: Handle, X, B, n):
+    """In place on B: B := (X^T X)^{-1} B for column-major batches X (batch, n, ldx) holding
+    upper factors and B (batch, m, ldb) holding n x m right-hand sides."""
+    import torch
+    ox = Operands(n, X)
+    batch, m = B.shape[0], B.shape[1]
+    ob = Operands(n, B)
+    nrhs = torch.full((batch,), m, dtype=torch.int32, device=B.device)
+    h.potrs_batched(batch, n, ox.n, m, nrhs, ox.ptrs[0], ox.lds[0], ob.ptrs[0], ob.lds[0], ob.info)
+    return ob
 
 
 class RaggedBatch:

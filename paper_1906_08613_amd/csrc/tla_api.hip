@@ -407,6 +407,32 @@ extern "C" tla_status tla_trlyap_batched(tla_handle h, tla_prec prec, int batch,
   return launch(h, TLA_TRLYAP, prec, pick_plan(h, TLA_TRLYAP, n_max, prec, batch), a);
 }
 
+extern "C" tla_status tla_potrs_batched(tla_handle h, int batch, int n_max, const int* n, int nrhs_max,
+                                        const int* nrhs, const double* const* X, const int* ldx, double* const* B,
+                                        const int* ldb, int* info) {
+  tla_status s = common_checks(h, TLA_F64, batch, n_max);
+  if (s != TLA_OK || batch == 0) return s;
+  if (nrhs_max < 0) return TLA_E_ARG;
+  if (!n || !nrhs || !X || !ldx || !B || !ldb || !info) return TLA_E_ARG;
+  TLA_HIP(hipSetDevice(h->device));
+  KArgs a{};
+  a.batch = batch;
+  a.n_max = n_max;
+  a.n = n;
+  a.a = X;
+  a.lda = ldx;
+  a.c = B;
+  a.ldc = ldb;
+  a.info = info;
+  a.m = nrhs;
+  a.m_max = nrhs_max;
+  // one wave per 16-column tile of right-hand sides, up to 4
+  const int tiles = (nrhs_max + 15) / 16;
+  const int nwi = tiles <= 1 ? 0 : (tiles == 2 ? 1 : 2);
+  const int nw = 1 << nwi;
+  return launch_one(h, potrs_kernel(nwi), potrs_lds_bytes(nw), batch, nw, a);
+}
+
 // --------------------------------------------------------- plan control
 extern "C" tla_status tla_set_plan(tla_handle h, tla_op op, tla_prec prec, const tla_plan* plan) {
   if (!h || op < 0 || op > 2 || prec < 0 || prec > 3) return TLA_E_ARG;

@@ -29,6 +29,8 @@ struct KArgs {
   double* work;          // FP64 workspace, one slot per workgroup (mixed path), may be null
   long long work_stride; // doubles per slot in `work`
   int only_flagged;      // FP64 kernels: solve only instances whose stat asks for the FP64 path
+  const int* m;          // solve with the factor: right-hand sides per instance
+  int m_max;             // ... and their largest count
 };
 
 }  // namespace tla

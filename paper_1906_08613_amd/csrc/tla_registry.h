@@ -43,4 +43,8 @@ size_t large_lds_bytes();
 int large_waves();
 KFn inplace_kernel(int op, int var, int nwi);
 size_t inplace_lds_bytes(int nw);
+// Solve with the upper Cholesky factor (FP64, in place on B); nwi as above.
+// KArgs: a = factor, lda, c = B, ldc, m / m_max = right-hand sides.
+KFn potrs_kernel(int nwi);
+size_t potrs_lds_bytes(int nw);
 }  // namespace tla

@@ -796,6 +796,66 @@ TLA_DI void tile_trsv_strips(Tile<T, 16>& c, const VX& Xd, lds_t<T>* buf) {
   wave_fence();
 }
 
+// Left solve with an upper-triangular diagonal tile: c := Xd^{-1} c (back
+// substitution up every column), 16 x 16 tiles, strip schedule: lane (g, v)
+// holds rows 4g..4g+3 of column v; strips are finished from the last one up,
+// each with a 4 x 4 back substitution in registers, and the strips above
+// subtract Xd(strip g, strip G) times the finished strip.
+template <class T, class VX>
+TLA_DI void tile_trsm_u(Tile<T, 16>& c, const VX& Xd, lds_t<T>* buf) {
+  const int l = lane_id(), jc = tcol<16>(l), g = l >> 4, v = l & 15;
+  constexpr int LD = 17;
+  lds_t<T>* S = buf;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[trow<T, 16>(l, r) + jc * LD] = c.v[r];
+  T dg[4][4], rin[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int b = a + 1; b < 4; ++b) dg[a][b] = Xd(4 * g + a, 4 * g + b);
+    rin[a] = T(1) / Xd(4 * g + a, 4 * g + a);
+  }
+  wave_fence();
+  T y[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) y[a] = S[4 * g + a + v * LD];
+#pragma unroll
+  for (int G = 3; G >= 0; --G) {
+    if (g == G) {
+#pragma unroll
+      for (int a = 3; a >= 0; --a) {
+        T acc = y[a];
+#pragma unroll
+        for (int b = a + 1; b < 4; ++b) acc -= dg[a][b] * y[b];
+        y[a] = acc * rin[a];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) S[4 * G + a + v * LD] = y[a];
+    }
+    if (G == 0) break;
+    // Xd(4g + a, 4G + b), used by the strips g < G
+    T cf[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) cf[a][b] = Xd(4 * g + a, 4 * G + b);
+    wave_fence();
+    T z[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) z[b] = S[4 * G + b + v * LD];
+    if (g < G) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) y[a] -= cf[a][b] * z[b];
+    }
+  }
+  wave_fence();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c.v[r] = S[trow<T, 16>(l, r) + jc * LD];
+  wave_fence();
+}
+
 template <class T, int TB, class VX>
 TLA_DI void tile_trsm_ut(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) {
   if constexpr (TB == 16) tile_trsv_strips<T, false>(c, Xd, buf);
