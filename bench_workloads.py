@@ -10,6 +10,8 @@ ragged  : 65536 mixed instances (40% Cholesky, 30% Sylvester, 30% Lyapunov),
 large   : 256 instances at n = 256, 512, 1024, FP64, tuned variants.
 planner : autotuner timings for n = 3..128 and the MLP trained on them;
           regret of the learned picker on held-out n against the measured best.
+potrs   : solve with the Cholesky factor, FP64, n = 64, 16 right-hand sides,
+          8192 instances (the factor's consumer), with the CPU oracle on a sample.
 plan    : one operation (first of --ops) at --n, --batch, --prec with the plan
           given by --plan, timed by the library's own timer (for profiling
           one kernel).
@@ -316,6 +318,49 @@ def planner(a):
                       "regret_default_plan_mean": float(r_default.mean())}))
 
 
+def potrs(a):
+    import torch
+    import oracle
+    import paper_1906_08613_amd as tla
+    from paper_1906_08613_amd import inputs as I
+    n, m, batch = 64, 16, 8192
+    h = tla.Handle(0)
+    A = I.potrf_problem("potrs", n, batch)
+    dX = tla.to_device_cm(np.triu(A))
+    tla.potrf(h, dX, "f64")
+    X = tla.from_device_cm(dX)
+    B = np.random.default_rng(64).normal(size=(batch, n, m))
+    dB = tla.to_device_rect(B)
+    pristine = dB.clone()
+    ox, ob = tla.Operands(n, dX), tla.Operands(n, dB)
+    nrhs = torch.full((batch,), m, dtype=torch.int32, device="cuda")
+    ts = []
+    for _ in range(6):
+        dB.copy_(pristine)
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch)
+        e0.record()
+        h.potrs_batched(batch, n, ox.n, m, nrhs, ox.ptrs[0], ox.lds[0], ob.ptrs[0], ob.lds[0], ob.info)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    t = float(np.median(ts[1:]))
+    Y = tla.from_device_rect(dB[:8], n)
+    Yr, _ = oracle.potrs_batch(np.triu(X[:8]), B[:8])
+    fl = 2.0 * n * n * m                      # two triangular solves with m right-hand sides
+    by = (n * (n + 1) // 2 + 2 * n * m) * 8   # upper factor read, B read and written
+    sample = 1024
+    t0 = time.perf_counter()
+    oracle.potrs_batch(np.triu(X[:sample]), B[:sample], oracle.max_threads())
+    tc = time.perf_counter() - t0
+    print(json.dumps({"workload": f"potrs f64 n={n} nrhs={m} x{batch}", "solves_per_s": batch / t,
+                      "gflops": batch * fl / t / 1e9, "gbs": batch * by / t / 1e9,
+                      "hbm_frac": batch * by / t / 8e12, "ms": t * 1e3,
+                      "fwd_err_max": float(np.abs(Y - Yr).max() / np.abs(Yr).max()),
+                      "cpu_oracle_solves_per_s": sample / tc, "cpu_threads": oracle.max_threads()}))
+    h.close()
+
+
 def plan(a):
     import torch  # noqa: F401  (device context for the library)
     import paper_1906_08613_amd as tla
@@ -331,4 +376,4 @@ def plan(a):
 
 def run(a):
     {"potrf16": potrf16, "sweep": sweep, "ragged": ragged, "large": large, "planner": planner,
-     "plan": plan}[a.workload](a)
+     "potrs": potrs, "plan": plan}[a.workload](a)
