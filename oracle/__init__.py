@@ -66,6 +66,8 @@ def lib():
             "orc_potrf_batch": (None, [c_int, c_int, D, D, I, c_int]),
             "orc_potrs": (c_int, [c_int, c_int, D, c_int, D, c_int]),
             "orc_potrs_batch": (None, [c_int, c_int, c_int, D, D, I, c_int]),
+            "orc_potri": (c_int, [c_int, D, c_int, D, c_int]),
+            "orc_potri_batch": (None, [c_int, c_int, D, D, I, c_int]),
             "orc_trsyl_batch": (None, [c_int, c_int, D, D, D, D, I, c_int]),
             "orc_trlyap_batch": (None, [c_int, c_int, D, D, D, I, c_int]),
             "orc_eta_potrf_batch": (None, [c_int, c_int, D, D, D, c_int]),
@@ -120,6 +122,15 @@ def potrs(X, B):
     x = _cm(X)
     y = _cm(B).copy()   # the solve overwrites it; never the caller's array
     info = lib().orc_potrs(n, m, _dp(x), n, _dp(y), n)
+    return _from_cm(y), info
+
+
+def potri(X):
+    """(X^T X)^{-1}, full n x n, from the upper triangle of the factor X -> (Ainv, info)."""
+    n = X.shape[-1]
+    x = _cm(X)
+    y = np.zeros_like(x)
+    info = lib().orc_potri(n, _dp(x), n, _dp(y), n)
     return _from_cm(y), info
 
 
@@ -219,6 +230,15 @@ def potrs_batch(X, B, threads=0):
     y = _cm(B).copy()   # the solve overwrites it; never the caller's array
     info = np.zeros(b, dtype=np.int32)
     lib().orc_potrs_batch(b, n, m, _dp(x), _dp(y), _ip(info), threads)
+    return _from_cm(y), info
+
+
+def potri_batch(X, threads=0):
+    b, n = X.shape[0], X.shape[-1]
+    x = _cm(X)
+    y = np.zeros_like(x)
+    info = np.zeros(b, dtype=np.int32)
+    lib().orc_potri_batch(b, n, _dp(x), _dp(y), _ip(info), threads)
     return _from_cm(y), info
 
 

@@ -87,6 +87,18 @@ int orc_potrs(int n, int m, const double *X, int ldx, double *B, int ldb) {
 }
 
 /*
+ * Inverse from the upper Cholesky factor: A^{-1} = (X^T X)^{-1}, the full n x n
+ * matrix, obtained by solving with the factor for the columns of the
+ * identity (orc_potrs above).  Returns 0, or k > 0 when x_kk (1-based) is
+ * zero; Y is then the identity.
+ */
+int orc_potri(int n, const double *X, int ldx, double *Y, int ldy) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) E(Y, ldy, i, j) = i == j ? 1.0 : 0.0;
+  return orc_potrs(n, n, X, ldx, Y, ldy);
+}
+
+/*
  * Triangular Sylvester L X + X U = C (Fig. 2c).  Reads the lower triangle of
  * L and the upper triangle of U.  Column by column, top to bottom:
  *   x_ij = (c_ij - sum_{k<i} l_ik x_kj - sum_{k<j} x_ik u_kj) / (l_ii + u_jj)
@@ -326,6 +338,13 @@ void orc_potrs_batch(int batch, int n, int m, const double *X, double *B, int *i
   size_t sx = (size_t)n * n, sb = (size_t)n * m;
 #pragma omp parallel for schedule(dynamic, 4)
   for (int b = 0; b < batch; ++b) info[b] = orc_potrs(n, m, X + b * sx, n, B + b * sb, n);
+}
+
+void orc_potri_batch(int batch, int n, const double *X, double *Y, int *info, int threads) {
+  set_threads(threads);
+  size_t st = (size_t)n * n;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int b = 0; b < batch; ++b) info[b] = orc_potri(n, X + b * st, n, Y + b * st, n);
 }
 
 void orc_eta_potrf_batch(int batch, int n, const double *A, const double *X, double *eta, int threads) {

@@ -78,3 +78,47 @@ def test_batch_equals_single(orc):
     for k in range(b):
         Y, _ = orc.potrs(X[k], B[k])
         assert np.array_equal(Yb[k], Y)
+
+
+# ------------------------------------------------------------ inverse (potri)
+def test_inverse_diagonal_closed_form(orc):
+    d = np.array([2.0, 0.25, 3.0])
+    Y, info = orc.potri(np.diag(d))
+    assert info == 0
+    assert np.allclose(Y, np.diag(1.0 / d ** 2), rtol=1e-15, atol=0)
+
+
+def test_inverse_exact_unit_factor(orc):
+    # unit diagonal, integer entries: X^{-1} is an integer matrix and so is
+    # A^{-1} = X^{-1} X^{-T}; every intermediate is an exact integer
+    X = np.array([[1.0, 2.0, -1.0, 3.0],
+                  [0.0, 1.0, 4.0, -2.0],
+                  [0.0, 0.0, 1.0, 1.0],
+                  [0.0, 0.0, 0.0, 1.0]])
+    Xi = np.rint(np.linalg.inv(X))
+    assert np.array_equal(Xi @ X, np.eye(4))
+    Y, info = orc.potri(X)
+    assert info == 0
+    assert np.array_equal(Y, Xi @ Xi.T)
+
+
+@pytest.mark.parametrize("n", [1, 6, 13])
+def test_inverse_matches_elimination_and_residual(orc, n):
+    A = I.potrf_problem("potri-pin", n, 1)[0]
+    X, info = orc.potrf(A)
+    assert info == 0
+    Y, info = orc.potri(X)
+    assert info == 0
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        y, st = orc.gepp(A, e)
+        assert st == 0 and np.allclose(Y[:, j], y, rtol=0, atol=1e-13 * np.abs(y).max())
+    assert np.abs(A @ Y - np.eye(n)).max() <= 1e-13
+
+
+def test_inverse_zero_pivot(orc):
+    X = np.triu(np.ones((3, 3)))
+    X[1, 1] = 0.0
+    Y, info = orc.potri(X)
+    assert info == 2 and np.array_equal(Y, np.eye(3))
