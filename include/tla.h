@@ -137,6 +137,15 @@ tla_status tla_potrs_batched(tla_handle h, int batch, int n_max, const int *n, i
                              const double *const *X, const int *ldx, double *const *B, const int *ldb,
                              int *info);
 
+/* Inverse from the upper Cholesky factor, FP64: Y_b := (X_b^T X_b)^{-1}, the
+ * full n[b] x n[b] matrix (symmetric up to rounding), written to the
+ * caller's Y[b] (column-major, leading dimension ldy[b]) by solving with the
+ * factor for the columns of the identity.  X as for tla_potrs_batched.
+ * info[b]: 0; -1 bad n; -2 ldx or ldy < max(1, n); k > 0 when x_kk (1-based)
+ * is zero, Y_b then the identity.  Asynchronous on the handle's stream. */
+tla_status tla_potri_batched(tla_handle h, int batch, int n_max, const int *n, const double *const *X,
+                             const int *ldx, double *const *Y, const int *ldy, int *info);
+
 /* Mixed batch of all three operations and uneven n in one persistent launch
  * (captured as a HIP graph and replayed when the same descriptor array, batch
  * and precision come again).  d: tla_desc[batch]. */

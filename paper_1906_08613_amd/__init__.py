@@ -32,7 +32,7 @@ OPS = {"potrf": POTRF, "trsyl": TRSYL, "trlyap": TRLYAP}
 SYMBOLS = [
     "tla_create", "tla_destroy", "tla_set_stream", "tla_sync",
     "tla_potrf_batched", "tla_trsyl_batched", "tla_trlyap_batched", "tla_ragged_batched",
-    "tla_potrs_batched", "tla_set_plan", "tla_get_plan", "tla_num_candidates", "tla_candidate", "tla_variant_name",
+    "tla_potrs_batched", "tla_potri_batched", "tla_set_plan", "tla_get_plan", "tla_num_candidates", "tla_candidate", "tla_variant_name",
     "tla_tune", "tla_time_plan", "tla_save_table", "tla_load_table", "tla_set_picker",
     "tla_set_refine", "tla_status_string",
     "tla_mlp_num_params", "tla_mlp_num_features", "tla_mlp_features", "tla_mlp_set_params",
@@ -91,6 +91,7 @@ def lib():
             "tla_trlyap_batched": (I, [V, I, I, I, P, P, P, P, P, P, P]),
             "tla_ragged_batched": (I, [V, I, I, I, P, P, P]),
             "tla_potrs_batched": (I, [V, I, I, P, I, P, P, P, P, P, P]),
+            "tla_potri_batched": (I, [V, I, I, P, P, P, P, P, P]),
             "tla_set_plan": (I, [V, I, I, ctypes.POINTER(Plan)]),
             "tla_get_plan": (I, [V, I, I, I, I, ctypes.POINTER(Plan)]),
             "tla_num_candidates": (I, [I]),
@@ -186,6 +187,10 @@ class Handle:
     def potrs_batched(self, batch, n_max, n, nrhs_max, nrhs, X, ldx, B, ldb, info):
         check(lib().tla_potrs_batched(self.h, batch, n_max, _ptr(n), nrhs_max, _ptr(nrhs), _ptr(X), _ptr(ldx),
                                       _ptr(B), _ptr(ldb), _ptr(info)), "tla_potrs_batched")
+
+    def potri_batched(self, batch, n_max, n, X, ldx, Y, ldy, info):
+        check(lib().tla_potri_batched(self.h, batch, n_max, _ptr(n), _ptr(X), _ptr(ldx), _ptr(Y), _ptr(ldy),
+                                      _ptr(info)), "tla_potri_batched")
 
     def ragged_batched(self, prec, batch, n_max, desc, info, stat=None):
         check(lib().tla_ragged_batched(self.h, _prec(prec), batch, n_max, _ptr(desc), _ptr(info), _ptr(stat)),
@@ -402,6 +407,14 @@ def potrs(h: Handle, X, B, n):
     nrhs = torch.full((batch,), m, dtype=torch.int32, device=B.device)
     h.potrs_batched(batch, n, ox.n, m, nrhs, ox.ptrs[0], ox.lds[0], ob.ptrs[0], ob.lds[0], ob.info)
     return ob
+
+
+def potri(h: Handle, X, Y, n):
+    """Y := (X^T X)^{-1} for column-major batches X (batch, n, ldx) holding upper factors and
+    Y (batch, n, ldy)."""
+    ox, oy = Operands(n, X), Operands(n, Y)
+    h.potri_batched(ox.batch, n, ox.n, ox.ptrs[0], ox.lds[0], oy.ptrs[0], oy.lds[0], oy.info)
+    return oy
 
 
 class RaggedBatch:

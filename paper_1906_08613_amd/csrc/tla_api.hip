@@ -433,6 +433,31 @@ extern "C" tla_status tla_potrs_batched(tla_handle h, int batch, int n_max, cons
   return launch_one(h, potrs_kernel(nwi), potrs_lds_bytes(nw), batch, nw, a);
 }
 
+extern "C" tla_status tla_potri_batched(tla_handle h, int batch, int n_max, const int* n, const double* const* X,
+                                        const int* ldx, double* const* Y, const int* ldy, int* info) {
+  tla_status s = common_checks(h, TLA_F64, batch, n_max);
+  if (s != TLA_OK || batch == 0) return s;
+  if (!n || !X || !ldx || !Y || !ldy || !info) return TLA_E_ARG;
+  TLA_HIP(hipSetDevice(h->device));
+  KArgs a{};
+  a.batch = batch;
+  a.n_max = n_max;
+  a.n = n;
+  a.a = X;
+  a.lda = ldx;
+  a.c = Y;
+  a.ldc = ldy;
+  a.info = info;
+  a.m = n;  // n right-hand sides: the columns of the identity
+  a.m_max = n_max;
+  hipLaunchKernelGGL(potri_eye_kernel(), dim3(batch), dim3(256), 0, h->stream, a);
+  TLA_HIP(hipGetLastError());
+  const int tiles = (n_max + 15) / 16;
+  const int nwi = tiles <= 1 ? 0 : (tiles == 2 ? 1 : 2);
+  const int nw = 1 << nwi;
+  return launch_one(h, potrs_kernel(nwi), potrs_lds_bytes(nw), batch, nw, a);
+}
+
 // --------------------------------------------------------- plan control
 extern "C" tla_status tla_set_plan(tla_handle h, tla_op op, tla_prec prec, const tla_plan* plan) {
   if (!h || op < 0 || op > 2 || prec < 0 || prec > 3) return TLA_E_ARG;

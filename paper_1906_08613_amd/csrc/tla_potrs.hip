@@ -91,6 +91,20 @@ __global__ __launch_bounds__(NW * 64) void k_potrs(KArgs g) {
   if (threadIdx.x == 0) g.info[b] = 0;
 }
 
+// Y := I on every valid instance (the right-hand sides of the inverse).
+__global__ __launch_bounds__(256) void k_potri_eye(KArgs g) {
+  const int b = blockIdx.x;
+  const int n = g.n[b], ld = g.ldc[b];
+  if (n <= 0 || n > g.n_max || ld < n) return;
+  gbl_t<double>* Y = to_gbl(g.c[b]);
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int j = e / n, i = e - j * n;
+    Y[i + (size_t)j * ld] = i == j ? 1.0 : 0.0;
+  }
+}
+
+KFn potri_eye_kernel() { return reinterpret_cast<KFn>(&k_potri_eye); }
+
 KFn potrs_kernel(int nwi) {
   switch (nwi) {
     case 0: return reinterpret_cast<KFn>(&k_potrs<1>);

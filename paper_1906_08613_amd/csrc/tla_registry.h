@@ -47,4 +47,6 @@ size_t inplace_lds_bytes(int nw);
 // KArgs: a = factor, lda, c = B, ldc, m / m_max = right-hand sides.
 KFn potrs_kernel(int nwi);
 size_t potrs_lds_bytes(int nw);
+// Identity into c (n x n, ldc) of every valid instance; 256 threads.
+KFn potri_eye_kernel();
 }  // namespace tla

@@ -112,3 +112,33 @@ def test_ragged_sizes_and_edge_cases(h, orc):
             assert ir == 0 and rel(Y, Yr) <= TOL, idx
         elif n > 0 and m > 0:
             assert np.array_equal(Y, B_list[idx]), idx      # rejected or singular: untouched
+
+
+@pytest.mark.parametrize("n", [1, 17, 64, 100])
+def test_inverse_parity(h, orc, n):
+    batch = 3
+    A, X = factors(orc, n, batch, f"potri-{n}")
+    Yr, ir = orc.potri_batch(X)
+    dX = tla.to_device_cm(X)
+    dY = torch.full((batch, n, n), 7.0, dtype=torch.float64, device="cuda")
+    print(f"potri n={n}", flush=True)
+    ops = tla.potri(h, dX, dY, n)
+    torch.cuda.synchronize()
+    assert np.all(ops.info.cpu().numpy() == 0)
+    Y = tla.from_device_cm(dY)
+    for k in range(batch):
+        assert rel(Y[k], Yr[k]) <= TOL, (n, k)
+        assert np.abs(A[k] @ Y[k] - np.eye(n)).max() <= 1e-12
+
+
+def test_inverse_zero_pivot_gives_identity(h, orc):
+    n = 20
+    A, X = factors(orc, n, 2, "potri-zero")
+    X = X.copy()
+    X[1, 7, 7] = 0.0
+    dX = tla.to_device_cm(X)
+    dY = torch.zeros((2, n, n), dtype=torch.float64, device="cuda")
+    ops = tla.potri(h, dX, dY, n)
+    torch.cuda.synchronize()
+    assert ops.info.cpu().tolist() == [0, 8]
+    assert np.array_equal(tla.from_device_cm(dY)[1], np.eye(n))
