@@ -194,25 +194,31 @@ def verify(orc, tla, benches, sample=48):
 
 
 def cpu_baseline(orc, benches_host, sample):
-    """The oracle as it stands, on a bounded sample, all host threads."""
+    """The oracle as it stands, on a bounded sample: all host threads, and one
+    thread on a quarter of the sample."""
+    def timed(threads, count):
+        total_t, total_solves, total_f = 0.0, 0, 0.0
+        for op, host in benches_host:
+            n = host[0].shape[-1]
+            sub = [m[:count] for m in host]
+            t0 = time.perf_counter()
+            if op == "potrf":
+                orc.potrf_batch(sub[0], threads)
+            elif op == "trsyl":
+                orc.trsyl_batch(*sub, threads)
+            else:
+                orc.trlyap_batch(*sub, threads)
+            total_t += time.perf_counter() - t0
+            total_solves += count
+            total_f += count * flops(op, n)
+        return total_solves / total_t, total_f / total_t / 1e9
     threads = orc.max_threads()
-    total_t, total_solves, total_f = 0.0, 0, 0.0
-    for op, host in benches_host:
-        n = host[0].shape[-1]
-        sub = [m[:sample] for m in host]
-        t0 = time.perf_counter()
-        if op == "potrf":
-            orc.potrf_batch(sub[0], threads)
-        elif op == "trsyl":
-            orc.trsyl_batch(*sub, threads)
-        else:
-            orc.trlyap_batch(*sub, threads)
-        total_t += time.perf_counter() - t0
-        total_solves += sample
-        total_f += sample * flops(op, n)
-    return {"value": total_solves / total_t, "unit": "solves/s", "cores": threads, "kind": "oracle",
+    v, gf = timed(threads, sample)
+    v1, gf1 = timed(1, max(sample // 4, 1))
+    return {"value": v, "unit": "solves/s", "cores": threads, "kind": "oracle",
             "sample": f"{sample} instances of each of {len(benches_host)} ops at the bench n, FP64 triple loops, "
-                      f"OpenMP over instances", "gflops": total_f / total_t / 1e9}
+                      f"OpenMP over instances; one-thread run on {max(sample // 4, 1)} of each",
+            "gflops": gf, "value_1thread": v1, "gflops_1thread": gf1}
 
 
 def lib_hash():
