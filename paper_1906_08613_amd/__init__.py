@@ -313,6 +313,14 @@ def variant_name(op, v):
     return lib().tla_variant_name(OPS.get(op, op), v).decode()
 
 
+def num_variants(op):
+    """Number of blocked-algorithm variants of op (names are valid for 0..count-1)."""
+    v = 0
+    while variant_name(op, v) != "invalid":
+        v += 1
+    return v
+
+
 # ---------------------------------------------------------- batch helpers
 def to_device_cm(M, device="cuda", ld=None):
     """numpy (batch, n, n) indexed [b, i, j] -> column-major batch tensor (batch, n, ld)."""

@@ -40,7 +40,9 @@ def _compile(src: str) -> str:
 def build(jobs: int | None = None, verbose: bool = True) -> str:
     os.makedirs(OBJ, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    # the mixed-precision kernel tables take longest: start them first
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")),
+                  key=lambda f: ("mixed" not in f, "trsyl" not in f, f))
     jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))

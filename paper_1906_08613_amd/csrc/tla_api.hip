@@ -19,11 +19,12 @@ using namespace tla;
 // ------------------------------------------------------------------ plans
 namespace tla {
 
-static const char* kVarNames[3][5] = {
-    {"right-looking", "left-looking", "bordered", nullptr, nullptr},
-    {"tile-wavefront", "rows-lazy", "rows-eager", "cols-lazy", "cols-eager"},
-    {"tile-wavefront", "rows-lazy", "right-looking", nullptr, nullptr}};
-static const int kNumVar[3] = {3, 5, 3};
+static const char* kVarNames[3][8] = {
+    {"right-looking", "left-looking", "bordered", nullptr, nullptr, nullptr, nullptr, nullptr},
+    {"tile-wavefront", "rows-lazy", "rows-eager", "cols-lazy", "cols-eager", "2d-bordered", "2d-border-lazy",
+     "2d-border-eager"},
+    {"tile-wavefront", "rows-lazy", "right-looking", "cols-lazy", nullptr, nullptr, nullptr, nullptr}};
+static const int kNumVar[3] = {3, 8, 4};  // CHOL_NVAR, SYL_NVAR, LYA_NVAR (checked where the kernels are listed)
 
 int num_variants(int op) { return (op >= 0 && op < 3) ? kNumVar[op] : 0; }
 

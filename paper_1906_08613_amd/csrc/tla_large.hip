@@ -22,6 +22,7 @@ __global__ __launch_bounds__(NW * 64) void k_trlyap_large(KArgs g) {
 
 template <int NW>
 static KFn inplace_kernel_nw(int op, int var) {
+  static_assert(CHOL_NVAR == 3 && SYL_NVAR == 8 && LYA_NVAR == 4, "one case per variant below");
   if (op == TLA_POTRF) {
     switch (var) {
       case 0: return reinterpret_cast<KFn>(&k_potrf_large<NW, 0>);
@@ -35,12 +36,16 @@ static KFn inplace_kernel_nw(int op, int var) {
       case 2: return reinterpret_cast<KFn>(&k_trsyl_large<NW, 2>);
       case 3: return reinterpret_cast<KFn>(&k_trsyl_large<NW, 3>);
       case 4: return reinterpret_cast<KFn>(&k_trsyl_large<NW, 4>);
+      case 5: return reinterpret_cast<KFn>(&k_trsyl_large<NW, 5>);
+      case 6: return reinterpret_cast<KFn>(&k_trsyl_large<NW, 6>);
+      case 7: return reinterpret_cast<KFn>(&k_trsyl_large<NW, 7>);
     }
   } else if (op == TLA_TRLYAP) {
     switch (var) {
       case 0: return reinterpret_cast<KFn>(&k_trlyap_large<NW, 0>);
       case 1: return reinterpret_cast<KFn>(&k_trlyap_large<NW, 1>);
       case 2: return reinterpret_cast<KFn>(&k_trlyap_large<NW, 2>);
+      case 3: return reinterpret_cast<KFn>(&k_trlyap_large<NW, 3>);
     }
   }
   return nullptr;

@@ -21,7 +21,7 @@
 
 namespace tla {
 
-constexpr int kMlpIn = 25, kMlpH = 64;
+constexpr int kMlpIn = 28, kMlpH = 64;
 constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kMlpH * kMlpIn, kOffW2 = kOffB1 + kMlpH, kOffB2 = kOffW2 + kMlpH * kMlpH,
               kOffW3 = kOffB2 + kMlpH, kOffB3 = kOffW3 + kMlpH, kMlpParams = kOffB3 + 1;
 
@@ -40,7 +40,7 @@ struct MlpState {
 
 // ----------------------------------------------------------------- features
 // op one-hot (3), precision one-hot (4), n terms (4), batch (1), variant
-// one-hot (5), tile 16 (1), matrix cores (1), waves one-hot (3), tile count
+// one-hot (8), tile 16 (1), matrix cores (1), waves one-hot (3), tile count
 // squared (1), coefficients through the caches (1), solved in place in global
 // memory (1).
 void mlp_features(int op, int n, int prec, int batch, const tla_plan& p, float* f) {
@@ -53,13 +53,13 @@ void mlp_features(int op, int n, int prec, int batch, const tla_plan& p, float* 
   f[9] = (nn / 128.f) * (nn / 128.f);
   f[10] = (float)((n + p.tile - 1) / p.tile) / 16.f;
   f[11] = std::log2((float)std::max(batch, 1)) / 16.f;
-  f[12 + std::min(p.variant, 4)] = 1.f;
-  f[17] = p.tile == 16 ? 1.f : 0.f;
-  f[18] = p.engine ? 1.f : 0.f;
-  f[19 + (p.waves == 1 ? 0 : (p.waves == 2 ? 1 : 2))] = 1.f;
-  f[22] = f[10] * f[10];
-  f[23] = (p.place == 1 || p.place == 2) ? 1.f : 0.f;
-  f[24] = p.place == 3 ? 1.f : 0.f;
+  f[12 + std::min(p.variant, 7)] = 1.f;
+  f[20] = p.tile == 16 ? 1.f : 0.f;
+  f[21] = p.engine ? 1.f : 0.f;
+  f[22 + (p.waves == 1 ? 0 : (p.waves == 2 ? 1 : 2))] = 1.f;
+  f[25] = f[10] * f[10];
+  f[26] = (p.place == 1 || p.place == 2) ? 1.f : 0.f;
+  f[27] = p.place == 3 ? 1.f : 0.f;
 }
 
 // ------------------------------------------------------------------ kernels

@@ -119,12 +119,32 @@ TLA_DI void potrf_blocked(const VA& A, const Ctx<T>& cx) {
 
 // ================================================ Sylvester L X + X U = C
 // X_IJ depends on X_KJ (K < I) through L and on X_IK (K < J) through U.
+// One-dimensional partitions (X split by block rows or block columns):
 //   SYL_WF  tile wavefront: all tiles with I + J = d at once, lazy updates.
 //   SYL_RL  block rows, lazy:  C_I -= L_{I,<I} X_{<I}; sweep the row block.
 //   SYL_RE  block rows, eager: sweep the row block; C_{>I} -= L_{>I,I} X_I.
 //   SYL_CL  block columns, lazy:  C_J -= X_{<J} U_{<J,J}; sweep the column.
 //   SYL_CE  block columns, eager: sweep the column; C_{>J} -= X_J U_{J,>J}.
-enum { SYL_WF = 0, SYL_RL = 1, SYL_RE = 2, SYL_CL = 3, SYL_CE = 4, SYL_NVAR = 5 };
+// Two-dimensional partition.  With X, C split into quadrants TL, TR, BL, BR
+// (L lower and U upper split conformally) the partitioned equation reads
+//   TL:  L_TL X_TL + X_TL U_TL = C_TL
+//   TR:  L_TL X_TR + X_TR U_BR = C_TR - X_TL U_TR
+//   BL:  L_BR X_BL + X_BL U_TL = C_BL - L_BL X_TL
+//   BR:  L_BR X_BR + X_BR U_BR = C_BR - L_BL X_TR - X_BL U_TR.
+// A loop that grows TL by one block row and column per step keeps one of
+// these states between steps, and each gives a variant:
+//   SYL_BD  only X_TL is solved: the step solves the new column above the
+//           diagonal and the new row left of it (independent of each other,
+//           two waves), then the diagonal tile ("bordered").
+//   SYL_BL  X_TL, X_TR and X_BL are solved, BR still holds C: the step solves
+//           the diagonal tile, then the rest of its block row (one wave) and
+//           of its block column (another wave), lazily.
+//   SYL_BE  as SYL_BL with BR kept updated (C_BR - L_BL X_TR - X_BL U_TR):
+//           after the row and column, C_{>K,>K} -= L_{>K,K} X_{K,>K} +
+//           X_{>K,K} U_{K,>K} over all waves (right-looking).
+// The states in which only one of TR and BL is solved give back the block
+// row and block column variants above.
+enum { SYL_WF = 0, SYL_RL = 1, SYL_RE = 2, SYL_CL = 3, SYL_CE = 4, SYL_BD = 5, SYL_BL = 6, SYL_BE = 7, SYL_NVAR = 8 };
 
 // Diagonal-tile coefficients of tile (I, J) (L_II and U_JJ), fetched before
 // the tile's updates so that their loads overlap the products.
@@ -195,6 +215,140 @@ TLA_DI void trsyl_blocked(const VX& X, const VL& L, const VU& U, const Ctx<T>& c
         __syncthreads();
       }
     }
+  } else if constexpr (VAR == SYL_BD) {
+    const int wr = NW > 1 ? 1 : 0;
+    for (int K = 0; K < nt; ++K) {
+      // the finished part of every border tile's update, spread over the waves:
+      // column tiles (I, K), I < K, take X_{I,<K} U_{<K,K}; row tiles (K, J),
+      // J < K, take L_{K,<K} X_{<K,J}
+      for (int t = w; t < 2 * K; t += NW) {
+        const bool col = t < K;
+        const int I = col ? t : K, J = col ? K : t - K;
+        Tile<T, TB> c;
+        tload(c, X.sub(I * TB, J * TB));
+        if (col) gemm_sum<G>(c, 0, K, [&](int P) { return X.sub(I * TB, P * TB); }, [&](int P) { return U.sub(P * TB, K * TB); });
+        else gemm_sum<G>(c, 0, K, [&](int P) { return L.sub(K * TB, P * TB); }, [&](int P) { return X.sub(P * TB, J * TB); });
+        tstore(c, X.sub(I * TB, J * TB));
+      }
+      __syncthreads();
+      // column above the diagonal, downwards (one wave) and row left of it,
+      // rightwards (another wave)
+      if (w == 0) {
+        for (int I = 0; I < K; ++I) {
+          const auto k = syl_tile_fetch<T, TB>(L, U, I, K);
+          Tile<T, TB> c;
+          tload(c, X.sub(I * TB, K * TB));
+          gemm_sum<G>(c, 0, I, [&](int P) { return L.sub(I * TB, P * TB); }, [&](int P) { return X.sub(P * TB, K * TB); });
+          syl_tile_solve_k<T, TB>(c, k, cx, I, K);
+          tstore(c, X.sub(I * TB, K * TB));
+        }
+      }
+      if (w == wr) {
+        for (int J = 0; J < K; ++J) {
+          const auto k = syl_tile_fetch<T, TB>(L, U, K, J);
+          Tile<T, TB> c;
+          tload(c, X.sub(K * TB, J * TB));
+          gemm_sum<G>(c, 0, J, [&](int P) { return X.sub(K * TB, P * TB); }, [&](int P) { return U.sub(P * TB, J * TB); });
+          syl_tile_solve_k<T, TB>(c, k, cx, K, J);
+          tstore(c, X.sub(K * TB, J * TB));
+        }
+      }
+      __syncthreads();
+      if (w == 0) {
+        const auto k = syl_tile_fetch<T, TB>(L, U, K, K);
+        Tile<T, TB> c;
+        tload(c, X.sub(K * TB, K * TB));
+        gemm_sum<G>(c, 0, K, [&](int P) { return L.sub(K * TB, P * TB); }, [&](int P) { return X.sub(P * TB, K * TB); });
+        gemm_sum<G>(c, 0, K, [&](int P) { return X.sub(K * TB, P * TB); }, [&](int P) { return U.sub(P * TB, K * TB); });
+        syl_tile_solve_k<T, TB>(c, k, cx, K, K);
+        tstore(c, X.sub(K * TB, K * TB));
+      }
+      __syncthreads();
+    }
+  } else if constexpr (VAR == SYL_BL) {
+    const int wr = NW > 1 ? 1 : 0;
+    for (int K = 0; K < nt; ++K) {
+      // finished part of the border's updates; task 0 is the diagonal tile,
+      // whose update is complete, so its wave solves it at once
+      const int m = nt - K - 1;
+      for (int t = w; t < 2 * m + 1; t += NW) {
+        const int I = t <= m ? K : K + t - m, J = t <= m ? K + t : K;
+        Tile<T, TB> c;
+        tload(c, X.sub(I * TB, J * TB));
+        gemm_sum<G>(c, 0, K, [&](int P) { return L.sub(I * TB, P * TB); }, [&](int P) { return X.sub(P * TB, J * TB); });
+        gemm_sum<G>(c, 0, K, [&](int P) { return X.sub(I * TB, P * TB); }, [&](int P) { return U.sub(P * TB, J * TB); });
+        if (t == 0) syl_tile_solve<T, TB>(c, L, U, cx, K, K);
+        tstore(c, X.sub(I * TB, J * TB));
+      }
+      __syncthreads();
+      if (w == 0) {
+        for (int J = K + 1; J < nt; ++J) {
+          const auto k = syl_tile_fetch<T, TB>(L, U, K, J);
+          Tile<T, TB> c;
+          tload(c, X.sub(K * TB, J * TB));
+          gemm_sum<G>(c, K, J, [&](int P) { return X.sub(K * TB, P * TB); }, [&](int P) { return U.sub(P * TB, J * TB); });
+          syl_tile_solve_k<T, TB>(c, k, cx, K, J);
+          tstore(c, X.sub(K * TB, J * TB));
+        }
+      }
+      if (w == wr) {
+        for (int I = K + 1; I < nt; ++I) {
+          const auto k = syl_tile_fetch<T, TB>(L, U, I, K);
+          Tile<T, TB> c;
+          tload(c, X.sub(I * TB, K * TB));
+          gemm_sum<G>(c, K, I, [&](int P) { return L.sub(I * TB, P * TB); }, [&](int P) { return X.sub(P * TB, K * TB); });
+          syl_tile_solve_k<T, TB>(c, k, cx, I, K);
+          tstore(c, X.sub(I * TB, K * TB));
+        }
+      }
+      __syncthreads();
+    }
+  } else if constexpr (VAR == SYL_BE) {
+    const int wr = NW > 1 ? 1 : 0;
+    if (w == 0) {
+      Tile<T, TB> c;
+      tload(c, X.sub(0, 0));
+      syl_tile_solve<T, TB>(c, L, U, cx, 0, 0);
+      tstore(c, X.sub(0, 0));
+    }
+    __syncthreads();
+    for (int K = 0; K < nt; ++K) {
+      // row and column of the border; only updates from inside the border remain
+      if (w == 0) {
+        for (int J = K + 1; J < nt; ++J) {
+          const auto k = syl_tile_fetch<T, TB>(L, U, K, J);
+          Tile<T, TB> c;
+          tload(c, X.sub(K * TB, J * TB));
+          gemm_sum<G>(c, K, J, [&](int P) { return X.sub(K * TB, P * TB); }, [&](int P) { return U.sub(P * TB, J * TB); });
+          syl_tile_solve_k<T, TB>(c, k, cx, K, J);
+          tstore(c, X.sub(K * TB, J * TB));
+        }
+      }
+      if (w == wr) {
+        for (int I = K + 1; I < nt; ++I) {
+          const auto k = syl_tile_fetch<T, TB>(L, U, I, K);
+          Tile<T, TB> c;
+          tload(c, X.sub(I * TB, K * TB));
+          gemm_sum<G>(c, K, I, [&](int P) { return L.sub(I * TB, P * TB); }, [&](int P) { return X.sub(P * TB, K * TB); });
+          syl_tile_solve_k<T, TB>(c, k, cx, I, K);
+          tstore(c, X.sub(I * TB, K * TB));
+        }
+      }
+      __syncthreads();
+      // trailing update C_IJ -= L_IK X_KJ + X_IK U_KJ for I, J > K; task 0 is
+      // the next diagonal tile, which its wave then solves
+      const int m = nt - K - 1;
+      for (int t = w; t < m * m; t += NW) {
+        const int I = K + 1 + t / m, J = K + 1 + t % m;
+        Tile<T, TB> c;
+        tload(c, X.sub(I * TB, J * TB));
+        G::sub(c, L.sub(I * TB, K * TB), X.sub(K * TB, J * TB));
+        G::sub(c, X.sub(I * TB, K * TB), U.sub(K * TB, J * TB));
+        if (t == 0) syl_tile_solve<T, TB>(c, L, U, cx, I, J);
+        tstore(c, X.sub(I * TB, J * TB));
+      }
+      __syncthreads();
+    }
   } else {  // SYL_CL / SYL_CE
     for (int J = 0; J < nt; ++J) {
       if constexpr (VAR == SYL_CL) {
@@ -243,7 +397,13 @@ TLA_DI void trsyl_blocked(const VX& X, const VL& L, const VU& U, const Ctx<T>& c
 //           once, then a sweep along the row.
 //   LYA_RE  right-looking (eager) by block column: diagonal tile, the tiles
 //           below it, then the symmetric rank-2b update of the trailing part.
-enum { LYA_WF = 0, LYA_RL = 1, LYA_RE = 2, LYA_NVAR = 3 };
+//   LYA_CL  block columns, lazy: the updates from the finished columns for the
+//           whole block column at once (the diagonal tile is then complete and
+//           solved), then a sweep down the column.
+// With X symmetric the two-dimensional partition of the Sylvester case folds
+// onto the lower triangle: its "bordered" state is LYA_RL, the lazy and eager
+// border states are LYA_CL and LYA_RE.
+enum { LYA_WF = 0, LYA_RL = 1, LYA_RE = 2, LYA_CL = 3, LYA_NVAR = 4 };
 
 template <class T, int TB, class VL>
 TLA_DI auto lya_tile_fetch(const VL& L, int I, int J) {
@@ -324,6 +484,31 @@ TLA_DI void trlyap_blocked(const VX& X, const VL& L, const Ctx<T>& cx) {
           tload(c, X.sub(I * TB, J * TB));
           if (J == I) lya_colside<T, TB, ENG>(c, X, L, I, J, 0, I);
           lya_rowside<T, TB, ENG>(c, X, L, I, J, 0, J);
+          lya_tile_solve_k<T, TB>(c, X, k, cx, I, J);
+        }
+      }
+      __syncthreads();
+    }
+  } else if constexpr (VAR == LYA_CL) {
+    for (int J = 0; J < nt; ++J) {
+      // tiles (I, J), I >= J: the terms through the finished columns K < J,
+      // sum_{K<J} L_IK X_JK^T + X_IK L_JK^T; task 0 is the diagonal tile
+      for (int I = J + w; I < nt; I += NW) {
+        Tile<T, TB> c;
+        tload(c, X.sub(I * TB, J * TB));
+        lya_colside<T, TB, ENG>(c, X, L, I, J, 0, J);
+        lya_rowside<T, TB, ENG>(c, X, L, I, J, 0, J);
+        if (I == J) lya_tile_solve<T, TB>(c, X, L, cx, J, J);
+        else tstore(c, X.sub(I * TB, J * TB));
+      }
+      __syncthreads();
+      // down the column: the remaining terms sum_{J<=K<I} L_IK X_KJ
+      if (w == 0) {
+        for (int I = J + 1; I < nt; ++I) {
+          const auto k = lya_tile_fetch<T, TB>(L, I, J);
+          Tile<T, TB> c;
+          tload(c, X.sub(I * TB, J * TB));
+          lya_colside<T, TB, ENG>(c, X, L, I, J, J, I);
           lya_tile_solve_k<T, TB>(c, X, k, cx, I, J);
         }
       }

@@ -1,31 +1,32 @@
-// Mixed-precision trsyl kernels with f32 tile updates on the matrix cores (plus the FP32 vector-ALU engines).
+// Mixed-precision trsyl kernels with f32 tile updates on the matrix cores (the
+// FP32 vector-ALU engines, tile/engine index 0 and 1, are compiled in
+// tla_trsyl_mixed_f32_valu.hip and reached through the same entry point).
 // Index: (variant, tile/engine, waves, placement); placement 0: coefficients and FP64 solution in LDS; 1: coefficients read through the caches; 2: FP64 solution in the global workspace too.
 #include "tla_mixed.hpp"
 #include "tla_registry.h"
 
 namespace tla {
+KFn trsyl_mixed_kernel_f32_valu(int var, int te, int nwi, int pl);
 namespace {
 constexpr int kPL = 3;
-template <int VAR, int TE, int NWI, int PL>
+template <int VAR, int NWI, int PL>
 void fill(KFn* tab) {
-  constexpr int TB = TE == 0 ? 8 : 16;
-  constexpr int ENG = TE == 2 ? ENG_MFMA : ENG_VALU;
   constexpr int NW = NWI == 0 ? 1 : (NWI == 1 ? 2 : 4);
-  tab[((VAR * kNumTE + TE) * kNumNW + NWI) * kPL + PL] = reinterpret_cast<KFn>(&k_trsyl_mixed<TB, ENG, NW, VAR, PL == 0, PL == 2>);
-  if constexpr (PL + 1 < kPL) fill<VAR, TE, NWI, PL + 1>(tab);
-  else if constexpr (NWI + 1 < kNumNW) fill<VAR, TE, NWI + 1, 0>(tab);
-  else if constexpr (TE + 1 < kNumTE) fill<VAR, TE + 1, 0, 0>(tab);
-  else if constexpr (VAR + 1 < SYL_NVAR) fill<VAR + 1, 0, 0, 0>(tab);
+  tab[(VAR * kNumNW + NWI) * kPL + PL] = reinterpret_cast<KFn>(&k_trsyl_mixed<16, ENG_MFMA, NW, VAR, PL == 0, PL == 2>);
+  if constexpr (PL + 1 < kPL) fill<VAR, NWI, PL + 1>(tab);
+  else if constexpr (NWI + 1 < kNumNW) fill<VAR, NWI + 1, 0>(tab);
+  else if constexpr (VAR + 1 < SYL_NVAR) fill<VAR + 1, 0, 0>(tab);
 }
 }  // namespace
 
 KFn trsyl_mixed_kernel_f32(int var, int te, int nwi, int pl) {
-  static KFn tab[SYL_NVAR * kNumTE * kNumNW * kPL] = {};
+  static KFn tab[SYL_NVAR * kNumNW * kPL] = {};
   static bool init = false;
-  if (!init) { fill<0, 0, 0, 0>(tab); init = true; }
+  if (!init) { fill<0, 0, 0>(tab); init = true; }
   if (var < 0 || var >= SYL_NVAR || te < 0 || te >= kNumTE || nwi < 0 || nwi >= kNumNW || pl < 0 || pl >= kPL)
     return nullptr;
-  return tab[((var * kNumTE + te) * kNumNW + nwi) * kPL + pl];
+  if (te < 2) return trsyl_mixed_kernel_f32_valu(var, te, nwi, pl);
+  return tab[(var * kNumNW + nwi) * kPL + pl];
 }
 // Work matrices in the workspace (placement 3, and the sizes above the
 // LDS-resident ones): 16 x 16 tiles on the matrix cores, waves 1 / 2 / 4 / 16.
