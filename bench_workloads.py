@@ -1,5 +1,5 @@
 """The benchmark's secondary workloads (one JSON line each), run with
-python bench.py --workload {potrf16,sweep,ragged,large,planner}.
+python bench.py --workload {potrf16,sweep,ragged,large,planner,potrs,variants,plan}.
 
 potrf16 : FP64 Cholesky, 1024 instances at n = 16, replayed many times inside
           one HIP graph (the batch is too small to fill the GPU by itself).
@@ -12,6 +12,9 @@ planner : autotuner timings for n = 3..128 and the MLP trained on them;
           regret of the learned picker on held-out n against the measured best.
 potrs   : solve with the Cholesky factor, FP64, n = 64, 16 right-hand sides,
           8192 instances (the factor's consumer), with the CPU oracle on a sample.
+variants: best time of each blocked-algorithm variant (over tiles, engines,
+          waves and placements), FP64, n = 16 .. 1024: 4096 instances up to
+          n = 128, 256 above (one in-place plan per variant there).
 plan    : one operation (first of --ops) at --n, --batch, --prec with the plan
           given by --plan, timed by the library's own timer (for profiling
           one kernel).
@@ -374,6 +377,32 @@ def plan(a):
     h.close()
 
 
+def variants(a):
+    import torch  # noqa: F401  (device context for the library)
+    import paper_1906_08613_amd as tla
+    h = tla.Handle(0)
+    for op in ["potrf", "trsyl", "trlyap"]:
+        for n in [16, 32, 48, 64, 96, 128, 256, 512, 1024]:
+            batch = 4096 if n <= 128 else 256
+            cands = [tla.candidate(op, i) for i in range(tla.num_candidates(op))]
+            if n > 128:  # one kernel per variant above the LDS-resident sizes
+                cands = [c for c in cands if c.place == 3 and c.waves == 4]
+            best = {}
+            for p in cands:
+                try:
+                    t = h.time_plan(op, n, "f64", batch, p, reps=3)
+                except tla.TlaError:
+                    continue
+                if p.variant not in best or t < best[p.variant][0]:
+                    best[p.variant] = (t, list(p.astuple()))
+            win = min(best, key=lambda v: best[v][0])
+            print(json.dumps({"workload": f"{op} f64 n={n} x{batch}", "winner": tla.variant_name(op, win),
+                              "winner_plan": best[win][1],
+                              "us_per_variant": {tla.variant_name(op, v): round(best[v][0] * 1e6, 1)
+                                                 for v in sorted(best)}}), flush=True)
+    h.close()
+
+
 def run(a):
     {"potrf16": potrf16, "sweep": sweep, "ragged": ragged, "large": large, "planner": planner,
-     "potrs": potrs, "plan": plan}[a.workload](a)
+     "potrs": potrs, "variants": variants, "plan": plan}[a.workload](a)
