@@ -12,7 +12,8 @@ prepared before the timed region.
 Printed: one JSON line with solves/s over the three operations, GF/s with the
 nominal flop counts (n^3/3 and 2n^3), the FP64 path measured in the same run
 for comparison, the roofline fraction of the dominant kernel, and the CPU
-oracle timed on a bounded sample on the host cores.
+oracle timed on the host cores over the same instances (about ten seconds of
+whole passes on all threads, plus a one-thread pass over a quarter).
 """
 from __future__ import annotations
 
@@ -42,7 +43,8 @@ def parse():
     p.add_argument("--prec", default="mixed_f32", choices=["f64", "mixed_f32", "mixed_f16", "mixed_bf16"])
     p.add_argument("--no-fp64-compare", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=384)
+    p.add_argument("--cpu-seconds", type=float, default=10.0,
+                   help="wall time of the all-threads oracle run (whole passes over the step's instances)")
     p.add_argument("--ops", default="potrf,trsyl,trlyap")
     p.add_argument("--workload", default="headline",
                    choices=["headline", "potrf16", "sweep", "ragged", "large", "planner", "potrs", "variants", "plan"],
@@ -193,11 +195,12 @@ def verify(orc, tla, benches, sample=48):
     return out
 
 
-def cpu_baseline(orc, benches_host, sample):
-    """The oracle as it stands, on a bounded sample: all host threads, and one
-    thread on a quarter of the sample."""
-    def timed(threads, count):
-        total_t, total_solves, total_f = 0.0, 0, 0.0
+def cpu_baseline(orc, benches_host, seconds):
+    """The oracle as it stands on the host cores: the whole step's instances,
+    passed through repeatedly until about `seconds` of wall time, on all
+    threads; then one pass over a quarter of them on one thread."""
+    def one_pass(threads, count):
+        t, solves, fl = 0.0, 0, 0.0
         for op, host in benches_host:
             n = host[0].shape[-1]
             sub = [m[:count] for m in host]
@@ -208,17 +211,35 @@ def cpu_baseline(orc, benches_host, sample):
                 orc.trsyl_batch(*sub, threads)
             else:
                 orc.trlyap_batch(*sub, threads)
-            total_t += time.perf_counter() - t0
-            total_solves += count
-            total_f += count * flops(op, n)
-        return total_solves / total_t, total_f / total_t / 1e9
+            t += time.perf_counter() - t0
+            solves += count
+            fl += count * flops(op, n)
+        return t, solves, fl
     threads = orc.max_threads()
-    v, gf = timed(threads, sample)
-    v1, gf1 = timed(1, max(sample // 4, 1))
-    return {"value": v, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sample} instances of each of {len(benches_host)} ops at the bench n, FP64 triple loops, "
-                      f"OpenMP over instances; one-thread run on {max(sample // 4, 1)} of each",
-            "gflops": gf, "value_1thread": v1, "gflops_1thread": gf1}
+    batch = min(host[0].shape[0] for _, host in benches_host)
+    t = s_ = f = 0.0
+    reps = 0
+    while t < seconds and reps < 100:
+        dt, ds, df = one_pass(threads, batch)
+        t, s_, f, reps = t + dt, s_ + ds, f + df, reps + 1
+    small = max(batch // 4, 1)
+    t1, s1, f1 = one_pass(1, small)
+    return {"value": s_ / t, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole step ({batch} instances of each of {len(benches_host)} ops at the bench n) "
+                      f"passed {reps} times ({t:.1f} s) on {threads} threads, FP64 triple loops, OpenMP over "
+                      f"instances; one-thread pass over {small} of each ({t1:.1f} s)",
+            "gflops": f / t / 1e9, "value_1thread": s1 / t1, "gflops_1thread": f1 / t1 / 1e9,
+            "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def lib_hash():
@@ -315,7 +336,7 @@ def main():
                        "fp64_tflops": batch * flops(dom, n) / kern[dom] / 1e12}
     res["plans"] = {op: list(h.get_plan(op, n, a.prec, batch).astuple()) for op in ops}
     if not a.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(orc, hosts, min(a.cpu_sample, batch))
+        res["cpu_baseline"] = cpu_baseline(orc, hosts, a.cpu_seconds)
     print(json.dumps(res))
     h.close()
 
