@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 #include <vector>
 
 #include "tla_host.h"
@@ -140,75 +141,47 @@ struct RagVariants { int v[3]; };
 // Sylvester/Lyapunov operands (and, for the mixed kernels, PL == 2 puts the
 // FP64 solution of all three operations in the workspace; for FP64, PL == 3
 // solves all three in place in global memory).
+// Variants compiled into the ragged workers: Cholesky all three, Sylvester
+// the 1-D ones and the tile wavefront (0..4), Lyapunov 0..2.  One worker holds
+// every operation's bodies, so each further variant raises its register use;
+// with the 2-D Sylvester and the lazy-column Lyapunov variants the mixed
+// workers fell to one wave per SIMD.  The planner maps a tuned variant outside
+// these to the tile wavefront.
+constexpr int kRagVars[3] = {CHOL_NVAR, 5, 3};
+
+// Calls f(std::integral_constant<int, V>) for the variant V == v (v is
+// uniform over the workgroup; out-of-range values take the last variant).
+template <int V, int NV, class F>
+__device__ __forceinline__ void with_variant(int v, const F& f) {
+  if constexpr (V + 1 >= NV) {
+    f(std::integral_constant<int, V>{});
+  } else {
+    if (v == V) f(std::integral_constant<int, V>{});
+    else with_variant<V + 1, NV>(v, f);
+  }
+}
+
 template <int TB, int ENG, int NW, int MIXED, int PL>
 __device__ void rag_run(const KArgs& g, const Inst& in, int op, const RagVariants& rv, unsigned char* smem) {
   if constexpr (MIXED == 0 && PL == 3) {
     static_assert(TB == 16 && ENG == ENG_MFMA, "in-place workers use 16 x 16 matrix-core tiles");
-    if (op == TLA_POTRF) {
-      switch (rv.v[0]) {
-        case 0: potrf_inplace_body<NW, 0>(g, in, smem); break;
-        case 1: potrf_inplace_body<NW, 1>(g, in, smem); break;
-        default: potrf_inplace_body<NW, 2>(g, in, smem); break;
-      }
-    } else if (op == TLA_TRSYL) {
-      switch (rv.v[1]) {
-        case 0: trsyl_inplace_body<NW, 0>(g, in, smem); break;
-        case 1: trsyl_inplace_body<NW, 1>(g, in, smem); break;
-        case 2: trsyl_inplace_body<NW, 2>(g, in, smem); break;
-        case 3: trsyl_inplace_body<NW, 3>(g, in, smem); break;
-        default: trsyl_inplace_body<NW, 4>(g, in, smem); break;
-      }
-    } else {
-      switch (rv.v[2]) {
-        case 0: trlyap_inplace_body<NW, 0>(g, in, smem); break;
-        case 1: trlyap_inplace_body<NW, 1>(g, in, smem); break;
-        default: trlyap_inplace_body<NW, 2>(g, in, smem); break;
-      }
-    }
+    if (op == TLA_POTRF) with_variant<0, kRagVars[0]>(rv.v[0], [&](auto vc) { constexpr int V = decltype(vc)::value; potrf_inplace_body<NW, V>(g, in, smem); });
+    else if (op == TLA_TRSYL) with_variant<0, kRagVars[1]>(rv.v[1], [&](auto vc) { constexpr int V = decltype(vc)::value; trsyl_inplace_body<NW, V>(g, in, smem); });
+    else with_variant<0, kRagVars[2]>(rv.v[2], [&](auto vc) { constexpr int V = decltype(vc)::value; trlyap_inplace_body<NW, V>(g, in, smem); });
   } else if constexpr (MIXED == 0) {
-    if (op == TLA_POTRF) {
-      switch (rv.v[0]) {
-        case 0: potrf_f64_body<TB, ENG, NW, 0>(g, in, smem); break;
-        case 1: potrf_f64_body<TB, ENG, NW, 1>(g, in, smem); break;
-        default: potrf_f64_body<TB, ENG, NW, 2>(g, in, smem); break;
-      }
-    } else if (op == TLA_TRSYL) {
-      switch (rv.v[1]) {
-        case 0: trsyl_f64_body<TB, ENG, NW, 0, PL == 0>(g, in, smem); break;
-        case 1: trsyl_f64_body<TB, ENG, NW, 1, PL == 0>(g, in, smem); break;
-        case 2: trsyl_f64_body<TB, ENG, NW, 2, PL == 0>(g, in, smem); break;
-        case 3: trsyl_f64_body<TB, ENG, NW, 3, PL == 0>(g, in, smem); break;
-        default: trsyl_f64_body<TB, ENG, NW, 4, PL == 0>(g, in, smem); break;
-      }
-    } else {
-      switch (rv.v[2]) {
-        case 0: trlyap_f64_body<TB, ENG, NW, 0, PL == 0>(g, in, smem); break;
-        case 1: trlyap_f64_body<TB, ENG, NW, 1, PL == 0>(g, in, smem); break;
-        default: trlyap_f64_body<TB, ENG, NW, 2, PL == 0>(g, in, smem); break;
-      }
-    }
+    if (op == TLA_POTRF)
+      with_variant<0, kRagVars[0]>(rv.v[0], [&](auto vc) { constexpr int V = decltype(vc)::value; potrf_f64_body<TB, ENG, NW, V>(g, in, smem); });
+    else if (op == TLA_TRSYL)
+      with_variant<0, kRagVars[1]>(rv.v[1], [&](auto vc) { constexpr int V = decltype(vc)::value; trsyl_f64_body<TB, ENG, NW, V, PL == 0>(g, in, smem); });
+    else
+      with_variant<0, kRagVars[2]>(rv.v[2], [&](auto vc) { constexpr int V = decltype(vc)::value; trlyap_f64_body<TB, ENG, NW, V, PL == 0>(g, in, smem); });
   } else {
-    if (op == TLA_POTRF) {
-      switch (rv.v[0]) {
-        case 0: potrf_mixed_body<TB, ENG, NW, 0, PL == 2>(g, in, smem); break;
-        case 1: potrf_mixed_body<TB, ENG, NW, 1, PL == 2>(g, in, smem); break;
-        default: potrf_mixed_body<TB, ENG, NW, 2, PL == 2>(g, in, smem); break;
-      }
-    } else if (op == TLA_TRSYL) {
-      switch (rv.v[1]) {
-        case 0: trsyl_mixed_body<TB, ENG, NW, 0, PL == 0, PL == 2>(g, in, smem); break;
-        case 1: trsyl_mixed_body<TB, ENG, NW, 1, PL == 0, PL == 2>(g, in, smem); break;
-        case 2: trsyl_mixed_body<TB, ENG, NW, 2, PL == 0, PL == 2>(g, in, smem); break;
-        case 3: trsyl_mixed_body<TB, ENG, NW, 3, PL == 0, PL == 2>(g, in, smem); break;
-        default: trsyl_mixed_body<TB, ENG, NW, 4, PL == 0, PL == 2>(g, in, smem); break;
-      }
-    } else {
-      switch (rv.v[2]) {
-        case 0: trlyap_mixed_body<TB, ENG, NW, 0, PL == 0, PL == 2>(g, in, smem); break;
-        case 1: trlyap_mixed_body<TB, ENG, NW, 1, PL == 0, PL == 2>(g, in, smem); break;
-        default: trlyap_mixed_body<TB, ENG, NW, 2, PL == 0, PL == 2>(g, in, smem); break;
-      }
-    }
+    if (op == TLA_POTRF)
+      with_variant<0, kRagVars[0]>(rv.v[0], [&](auto vc) { constexpr int V = decltype(vc)::value; potrf_mixed_body<TB, ENG, NW, V, PL == 2>(g, in, smem); });
+    else if (op == TLA_TRSYL)
+      with_variant<0, kRagVars[1]>(rv.v[1], [&](auto vc) { constexpr int V = decltype(vc)::value; trsyl_mixed_body<TB, ENG, NW, V, PL == 0, PL == 2>(g, in, smem); });
+    else
+      with_variant<0, kRagVars[2]>(rv.v[2], [&](auto vc) { constexpr int V = decltype(vc)::value; trlyap_mixed_body<TB, ENG, NW, V, PL == 0, PL == 2>(g, in, smem); });
   }
 }
 
@@ -354,7 +327,7 @@ static tla_status rag_plan(tla_ctx* h, int prec, int batch, int n_max, tla_stat*
         const int rep = std::min(cls == 0 ? 24 : (cls == 1 ? 48 : 96), n_max);
         const bool ok = h->picker != TLA_PICK_DEFAULT && table_pick(h, op, rep, prec, batch, &p) && p.tile == 16 &&
                         p.engine == 1;
-        L.rv.v[op] = ok ? p.variant : 0;
+        L.rv.v[op] = ok && p.variant < kRagVars[op] ? p.variant : 0;
       }
       const int eff_prec = pass == 1 ? TLA_F64 : prec;
       for (int op = 0; op < 3; ++op) {
