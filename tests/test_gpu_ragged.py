@@ -138,3 +138,30 @@ def test_ragged_invalid_descriptors(h):
     torch.cuda.synchronize()
     assert rb.info.cpu().tolist() == [0, -3, 0, -2, -1]
     assert np.allclose(np.triu(rb.result(0)), np.eye(4) * np.sqrt(2))
+
+
+def test_ragged_maps_uncompiled_variants_to_wavefront(h, tmp_path):
+    # a tuning table whose best Sylvester / Lyapunov variants are not compiled
+    # into the ragged workers: they run the tile wavefront, bit for bit the
+    # same as with the built-in default plans
+    ops, ns, mats = make_batch("rag-map", 60)
+    path = str(tmp_path / "t.txt")
+    lines = ["# op n prec batch variant tile engine waves place seconds"]
+    for n in range(4, 129, 4):
+        lines.append(f"0 {n} 0 60 0 16 1 2 0 1.0e-5")
+        lines.append(f"1 {n} 0 60 7 16 1 2 1 1.0e-5")
+        lines.append(f"2 {n} 0 60 3 16 1 2 1 1.0e-5")
+    open(path, "w").write("\n".join(lines) + "\n")
+    h2 = tla.Handle(0)
+    h2.load_table(path)
+    h2.set_picker(tla.PICK_TABLE)
+    rb_t = tla.RaggedBatch(ops, mats)
+    tla.ragged(h2, rb_t, "f64")
+    h2.set_picker(tla.PICK_DEFAULT)
+    rb_d = tla.RaggedBatch(ops, mats)
+    tla.ragged(h2, rb_d, "f64")
+    torch.cuda.synchronize()
+    assert np.all(rb_t.info.cpu().numpy() == 0)
+    for b in range(rb_t.batch):
+        assert np.array_equal(rb_t.result(b), rb_d.result(b)), (b, ops[b], ns[b])
+    h2.close()
