@@ -14,8 +14,12 @@ namespace tla {
 // In/out view of the caller's matrix for in-place solves.  Reads outside
 // n x n return the padding (1 on the diagonal for the Cholesky pivots, 0
 // elsewhere) and writes there are dropped.  upper_only (Cholesky): the strict
-// lower triangle is neither read (reads return 0) nor written.
-template <class T>
+// lower triangle is neither read (reads return 0) nor written.  SYM
+// (Lyapunov): the matrix is symmetric and held by its lower triangle, so a
+// read above the diagonal returns the mirrored element, and mirrors() tells
+// the tile solvers to store every solved tile below the diagonal also
+// transposed above it.
+template <class T, bool SYM = false>
 struct IOView {
   double* p;
   int ld, n;
@@ -29,6 +33,9 @@ struct IOView {
   TLA_DI T operator()(int i, int j) const {
     int r, c;
     coords(i, j, r, c);
+    if constexpr (SYM) {
+      if (r < c) { const int t = r; r = c; c = t; }
+    }
     const bool in = r < n && c < n;
     const int rr = r < n ? r : n - 1, cc = c < n ? c : n - 1;
     const double raw = to_gbl(p)[rr + (size_t)cc * ld];
@@ -41,6 +48,7 @@ struct IOView {
     if (r < n && c < n && !(upper_only && r > c)) to_gbl(p)[r + (size_t)c * ld] = double(v);
   }
   TLA_DI void fence() const { __threadfence_block(); }
+  static constexpr bool mirrors() { return SYM; }
   TLA_DI IOView sub(int i0, int j0) const {
     IOView v = *this;
     if (tr) { v.r0 += j0; v.c0 += i0; } else { v.r0 += i0; v.c0 += j0; }
@@ -99,14 +107,6 @@ TLA_DI void trsyl_inplace_body(const KArgs& g, const Inst& in, unsigned char* sm
   }
 }
 
-// mirrors the lower triangle of the caller's n x n matrix into its upper one
-template <int NW>
-TLA_DI void mirror_global(double* p, int ld, int n) {
-  gbl_t<double>* q = to_gbl(p);
-  for (int j = wave_id(); j < n; j += NW)
-    for (int i = lane_id(); i < j; i += 64) q[i + (size_t)j * ld] = q[j + (size_t)i * ld];
-}
-
 template <int NW, int VAR>
 TLA_DI void trlyap_inplace_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
@@ -117,12 +117,10 @@ TLA_DI void trlyap_inplace_body(const KArgs& g, const Inst& in, unsigned char* s
   large_ctx_init<NW>(smem, cx, n, s_info, INT_MAX);
   const GView<double> L = gview<double>(in.a, in.lda, n, -1);
   scan_zero_denoms(L, L, n, true, s_info);
-  // S is given by its lower triangle; the diagonal tiles are used in full
-  mirror_global<NW>(in.c, in.ldc, n);
-  __syncthreads();
-  trlyap_blocked<double, kLargeTB, ENG_MFMA, NW, VAR>(ioview<double>(in.c, in.ldc, n, false), L, cx);
-  __syncthreads();
-  mirror_global<NW>(in.c, in.ldc, n);
+  // S is given by its lower triangle: the view reads the diagonal tiles'
+  // upper halves from it, and the solved tiles are stored on both sides
+  const IOView<double, true> X{in.c, in.ldc, n, false, 0, 0, false};
+  trlyap_blocked<double, kLargeTB, ENG_MFMA, NW, VAR>(X, L, cx);
   __syncthreads();
   if (threadIdx.x == 0) {
     *in.info = *s_info == INT_MAX ? 0 : *s_info;

@@ -137,6 +137,31 @@ TLA_DI bool all_finite(const T* Wg, int ldw, int n) {
   return ok;
 }
 
+// Writes the symmetric n x n result held in the lower triangle of a global
+// work matrix (leading dimension ldx) to the caller's matrix, by 16 x 16
+// tiles: each tile below the diagonal is stored in place and transposed
+// above it (both stores coalesced), a diagonal tile from its lower triangle.
+// Reads and writes outside n x n are clamped or dropped.
+template <int NW>
+TLA_DI void egress_sym_tiles(double* Gg, int ldg, int n, const double* Xg, int ldx) {
+  const GView<double> X = gview<double>(Xg, ldx, n, 0);
+  gbl_t<double>* G = to_gbl(Gg);
+  const int nt = (n + 15) / 16, l = lane_id(), j = tcol<16>(l);
+  for (int t = wave_id(); t < nt * nt; t += NW) {
+    const int I = t / nt, J = t - I * nt;
+    if (I < J) continue;
+    Tile<double, 16> c;
+    tload(c, X.sub(I * 16, J * 16));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = trow<double, 16>(l, r), gi = I * 16 + i, gj = J * 16 + j;
+      if (gi >= n || gj >= n || (I == J && i < j)) continue;
+      G[gi + (size_t)gj * ldg] = c.v[r];
+      if (gi != gj) G[gj + (size_t)gi * ldg] = c.v[r];
+    }
+  }
+}
+
 // ===================================================== Sylvester, mixed
 template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG, bool WG = false>
 TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem) {
@@ -284,7 +309,9 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
       for (int e = threadIdx.x; e < np * ld; e += blockDim.x) m.Xd[e] = double(m.W[e]);
       __syncthreads();
       for (;;) {
-        // R = S - L Xd - Xd L^T on the lower tiles (Xd is kept symmetric)
+        // R = S - L Xd - Xd L^T on the lower tiles.  Only Xd's lower tiles
+        // are read (a tile above the diagonal as the transpose of its mirror),
+        // and its diagonal tiles are kept exactly symmetric
         double sr = 0.0, sx = 0.0;
         const auto Xv = xcolmajor<XG>(m.Xd, ld);
         for (int t = wave_id(); t < nt * nt; t += NW) {
@@ -294,7 +321,8 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
           tload(c, S64.sub(I * TB, J * TB));
           tload(x, Xv.sub(I * TB, J * TB));
           typedef Gemm<double, TB, E64> G64;
-          gemm_sum<G64>(c, 0, I + 1, [&](int K) { return L64.sub(I * TB, K * TB); }, [&](int K) { return Xv.sub(K * TB, J * TB); });
+          gemm_sum<G64>(c, 0, I + 1, [&](int K) { return L64.sub(I * TB, K * TB); },
+                        [&](int K) { return K >= J ? Xv.sub(K * TB, J * TB) : Xv.sub(J * TB, K * TB).t(); });
           gemm_sum<G64>(c, 0, J + 1, [&](int K) { return Xv.sub(I * TB, K * TB); }, [&](int K) { return L64.sub(J * TB, K * TB).t(); });
           const double wgt = I == J ? 1.0 : 2.0;
           const int l = lane_id(), j = tcol<TB>(l);
@@ -314,13 +342,12 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
         if constexpr (LU_LDS) trlyap_blocked<float, TB, ENG, NW, VAR>(xcolmajor<WG>(m.W, ld), colmajor(m.A1, ld), cx);
         else trlyap_blocked<float, TB, ENG, NW, VAR>(xcolmajor<WG>(m.W, ld), gview<float>(Lg, ldl, n, -1), cx);
         __syncthreads();
-        // Xd += D on the lower triangle, then keep Xd symmetric
+        // Xd += D on the lower tiles and on both halves of the diagonal tiles
+        // (D's diagonal tiles are exactly symmetric, so Xd's stay so)
         for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
           const int j = e / np, i = e - j * np;
-          if (i >= j) m.Xd[i + j * ld] += double(m.W[i + j * ld]);
+          if (i >= j || i / TB == j / TB) m.Xd[i + j * ld] += double(m.W[i + j * ld]);
         }
-        __syncthreads();
-        mirror_lower<double, !XG>(m.Xd, ld, np);
         ++st.it;
         __syncthreads();
       }
@@ -338,7 +365,10 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
     trlyap_blocked<double, TB, ENG64, NW, VAR>(xcolmajor<XG>(m.Xd, ld), L64, cd);
     __syncthreads();
   }
-  if (info0 == 0 && !(XG && fb)) egress<double, NW, !XG>(Sg, lds, n, m.Xd, ld, 2);
+  if (info0 == 0 && !(XG && fb)) {
+    if constexpr (XG) egress_sym_tiles<NW>(Sg, lds, n, m.Xd, ld);
+    else egress<double, NW, true>(Sg, lds, n, m.Xd, ld, 2);
+  }
   if (threadIdx.x == 0) *in.info = info0;
   write_stat(in, st);
 }

@@ -426,6 +426,7 @@ TLA_DI void lya_tile_solve_k(Tile<T, TB>& c, const VX& X, const K& k, const Ctx<
     X.fence();
   } else {
     tstore(c, X.sub(I * TB, J * TB));
+    if constexpr (VX::mirrors()) tstore(c, X.sub(J * TB, I * TB).t());
   }
 }
 template <class T, int TB, class VX, class VL>

@@ -68,6 +68,8 @@ struct View {
   TLA_DI void store(int i, int j, T v) const { p[i * rs + j * cs] = v; }
   TLA_DI View sub(int i0, int j0) const { return View{p + i0 * rs + j0 * cs, rs, cs}; }
   TLA_DI View t() const { return View{p, cs, rs}; }
+  // symmetric matrices in a View are mirrored by the caller, not on store
+  static constexpr bool mirrors() { return false; }
   // Makes this wave's stores visible to its other lanes before they read:
   // the LDS serves a wave in order; global stores need to complete first.
   TLA_DI void fence() const {
