@@ -39,6 +39,10 @@ TLA_DI int wave_id() { return threadIdx.x >> 6; }
 // wave's requests in issue order, so waiting for the outstanding ones and
 // stopping the compiler from moving memory accesses across is enough.
 TLA_DI void wave_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// Orders this thread's LDS accesses in the compiled code only.  Enough between
+// a wave's LDS writes and its later reads of other lanes' values: the LDS
+// serves one wave's accesses in the order they were issued.
+TLA_DI void compiler_fence() { asm volatile("" ::: "memory"); }
 
 // --------------------------------------------------------------- views
 // LDS-qualified element type: accesses through it compile to ds_read /
@@ -347,9 +351,11 @@ TLA_DI void tile_sylv_elem(Tile<T, TB>& c, const VL& Lt, const VU& Ut, lds_t<T>*
 //   L_II X_IJ + X_IJ U_JJ = C_IJ - sum_{K<I} L_IK X_KJ - sum_{K<J} X_IK U_KJ,
 // a 2 x 2 Sylvester system solved in registers once the block anti-diagonal
 // I + J - 1 has been subtracted.  Step D subtracts the blocks of anti-diagonal
-// D (published in cb / rb) and finalises anti-diagonal D + 1.  Staged
-// coefficient blocks are zero outside the strict block triangles and the
-// broadcast blocks start at zero, as in the element schedule.
+// D (published in cb / rb) and finalises anti-diagonal D + 1.  A lane reads
+// a coefficient block and its broadcast partner only at the steps where their
+// product is nonzero (a quarter of them on average); the LDS reads of the
+// other lanes are masked off, which lowers the LDS traffic of a full compute
+// unit.
 template <int TB>
 TLA_DI int blk2_index(int i, int j) {  // element (i, j) of a tile stored as 2 x 2 blocks
   return 4 * ((TB / 2) * (i >> 1) + (j >> 1)) + 2 * (i & 1) + (j & 1);
@@ -407,13 +413,6 @@ TLA_DI void tile_sylv_blk2(Tile<T, 16>& c, const Blk2Coef<T>& k, lds_t<T>* buf, 
     Lb[4 * l + e] = J < I ? k.lv[e] : T(0);
     Ub[4 * l + e] = I < J ? k.uv[e] : T(0);
   }
-  if (l < 8) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      cb[4 * l + e] = T(0);
-      rb[4 * l + e] = T(0);
-    }
-  }
   const T l00 = k.l00, l10 = k.l10, l11 = k.l11, u00 = k.u00, u01 = k.u01, u11 = k.u11;
   const bool r0 = i0 < ni, r1 = i0 + 1 < ni, c0 = j0 < nj, c1 = j0 + 1 < nj;
   const T q00 = (r0 && c0) ? T(1) / (l00 + u00) : T(0);
@@ -439,27 +438,32 @@ TLA_DI void tile_sylv_blk2(Tile<T, 16>& c, const Blk2Coef<T>& k, lds_t<T>* buf, 
   }
 #pragma unroll 1
   for (int D = 0; D < 14; ++D) {
-    int K = D - J, K2 = D - I;
-    K = (K >= 0 && K < 8) ? K : I;  // out of range: a zero block of Lb
-    K2 = (K2 >= 0 && K2 < 8) ? K2 : J;
-    T lk[4], uk[4];
+    // a lane reads a block pair only when its product is nonzero: L_IK with
+    // K = D - J < I (X_KJ finalised at the last step), U_K'J with K' = D - I < J
+    const int K = D - J, K2 = D - I;
+    T lk[4] = {T(0), T(0), T(0), T(0)}, uk[4] = {T(0), T(0), T(0), T(0)};
+    T xc[4] = {T(0), T(0), T(0), T(0)}, xr[4] = {T(0), T(0), T(0), T(0)};
+    compiler_fence();
+    if (K >= 0 && K < I) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      lk[e] = Lb[4 * (8 * I + K) + e];
-      uk[e] = Ub[4 * (8 * K2 + J) + e];
+      for (int e = 0; e < 4; ++e) {
+        lk[e] = Lb[4 * (8 * I + K) + e];
+        xc[e] = cb[4 * J + e];
+      }
     }
-    wave_fence();
-    T xc[4], xr[4];
+    if (K2 >= 0 && K2 < J) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      xc[e] = cb[4 * J + e];
-      xr[e] = rb[4 * I + e];
+      for (int e = 0; e < 4; ++e) {
+        uk[e] = Ub[4 * (8 * K2 + J) + e];
+        xr[e] = rb[4 * I + e];
+      }
     }
     // c -= L_IK X_KJ + X_IK' U_K'J on row-major 2 x 2 blocks
     x[0] -= lk[0] * xc[0] + lk[1] * xc[2] + xr[0] * uk[0] + xr[1] * uk[2];
     x[1] -= lk[0] * xc[1] + lk[1] * xc[3] + xr[0] * uk[1] + xr[1] * uk[3];
     x[2] -= lk[2] * xc[0] + lk[3] * xc[2] + xr[2] * uk[0] + xr[3] * uk[2];
     x[3] -= lk[2] * xc[1] + lk[3] * xc[3] + xr[2] * uk[1] + xr[3] * uk[3];
+    compiler_fence();
     if (I + J == D + 1) {
       finalise();
 #pragma unroll
