@@ -574,7 +574,7 @@ TLA_DI void tile_potf2_strip(Tile<T, 16>& c, lds_t<T>* buf, int nv, int base, ld
   lds_t<T>* S = buf;  // the tile, column-major, leading dimension 17
 #pragma unroll
   for (int r = 0; r < 4; ++r) S[trow<T, 16>(l, r) + j * LD] = c.v[r];
-  wave_fence();
+  compiler_fence();
   T a[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) a[e] = S[4 * g + e + j * LD];
@@ -644,15 +644,15 @@ TLA_DI void tile_potf2_strip(Tile<T, 16>& c, lds_t<T>* buf, int nv, int base, ld
 #pragma unroll
       for (int e = 0; e < 4; ++e) S[4 * g + e + j * LD] = a[e];
     }
-    wave_fence();
+    compiler_fence();
   }
   if (l == 0 && bad != 0 && *info == 0) *info = bad;
 #pragma unroll
   for (int e = 0; e < 4; ++e) S[4 * g + e + j * LD] = a[e];
-  wave_fence();
+  compiler_fence();
 #pragma unroll
   for (int r = 0; r < 4; ++r) c.v[r] = S[trow<T, 16>(l, r) + j * LD];
-  wave_fence();
+  compiler_fence();
 }
 
 template <class T, int TB>
@@ -761,7 +761,7 @@ TLA_DI void tile_trsv_strips(Tile<T, 16>& c, const VX& Xd, lds_t<T>* buf) {
     for (int b = 0; b < a; ++b) dg[a][b] = Xd(4 * g + b, 4 * g + a);
     rin[a] = T(1) / Xd(4 * g + a, 4 * g + a);
   }
-  wave_fence();
+  compiler_fence();
   T y[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) y[a] = S[(4 * g + a) * rs + v * cs];
@@ -785,7 +785,7 @@ TLA_DI void tile_trsv_strips(Tile<T, 16>& c, const VX& Xd, lds_t<T>* buf) {
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) cf[a][b] = Xd(4 * G + b, 4 * g + a);
-    wave_fence();
+    compiler_fence();
     T z[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) z[b] = S[(4 * G + b) * rs + v * cs];
@@ -796,10 +796,10 @@ TLA_DI void tile_trsv_strips(Tile<T, 16>& c, const VX& Xd, lds_t<T>* buf) {
         for (int b = 0; b < 4; ++b) y[a] -= cf[a][b] * z[b];
     }
   }
-  wave_fence();
+  compiler_fence();
 #pragma unroll
   for (int r = 0; r < 4; ++r) c.v[r] = S[trow<T, 16>(l, r) + jc * LD];
-  wave_fence();
+  compiler_fence();
 }
 
 // Left solve with an upper-triangular diagonal tile: c := Xd^{-1} c (back
@@ -821,7 +821,7 @@ TLA_DI void tile_trsm_u(Tile<T, 16>& c, const VX& Xd, lds_t<T>* buf) {
     for (int b = a + 1; b < 4; ++b) dg[a][b] = Xd(4 * g + a, 4 * g + b);
     rin[a] = T(1) / Xd(4 * g + a, 4 * g + a);
   }
-  wave_fence();
+  compiler_fence();
   T y[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) y[a] = S[4 * g + a + v * LD];
@@ -845,7 +845,7 @@ TLA_DI void tile_trsm_u(Tile<T, 16>& c, const VX& Xd, lds_t<T>* buf) {
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) cf[a][b] = Xd(4 * g + a, 4 * G + b);
-    wave_fence();
+    compiler_fence();
     T z[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) z[b] = S[4 * G + b + v * LD];
@@ -856,10 +856,10 @@ TLA_DI void tile_trsm_u(Tile<T, 16>& c, const VX& Xd, lds_t<T>* buf) {
         for (int b = 0; b < 4; ++b) y[a] -= cf[a][b] * z[b];
     }
   }
-  wave_fence();
+  compiler_fence();
 #pragma unroll
   for (int r = 0; r < 4; ++r) c.v[r] = S[trow<T, 16>(l, r) + jc * LD];
-  wave_fence();
+  compiler_fence();
 }
 
 template <class T, int TB, class VX>
