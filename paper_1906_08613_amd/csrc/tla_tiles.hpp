@@ -511,12 +511,35 @@ TLA_DI void tile_sylv(Tile<T, TB>& c, const VL& Lt, const VU& Ut, lds_t<T>* buf,
   sylv_solve<T, TB>(c, sylv_fetch<T, TB>(Lt, Ut), buf, ni, nj);
 }
 
+// Square root of a pivot and its reciprocal for the Cholesky tiles, without
+// the long dependent chains of a correctly rounded square root followed by a
+// division: the hardware reciprocal square root estimate is refined by
+// Newton-Raphson steps y <- y + y (1 - p y^2) / 2, the root s = p y is
+// corrected once with its exact residual p - s^2 (fused multiply-add;
+// Markstein's final step), and the reciprocal by one Newton step from y.
+// Exact square roots (perfect squares) come out exact.
+TLA_DI void pivot_root(double p, double& s, double& r) {
+  double y = __builtin_amdgcn_rsq(p);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = __builtin_fma(0.5 * y, __builtin_fma(-p * y, y, 1.0), y);
+  s = p * y;
+  s = __builtin_fma(__builtin_fma(-s, s, p), 0.5 * y, s);
+  r = __builtin_fma(y, __builtin_fma(-s, y, 1.0), y);
+}
+TLA_DI void pivot_root(float p, float& s, float& r) {
+  float y = __builtin_amdgcn_rsqf(p);
+  y = __builtin_fmaf(0.5f * y, __builtin_fmaf(-p * y, y, 1.0f), y);
+  s = p * y;
+  s = __builtin_fmaf(__builtin_fmaf(-s, s, p), 0.5f * y, s);
+  r = __builtin_fmaf(y, __builtin_fmaf(-s, y, 1.0f), y);
+}
+
 // ---- Upper Cholesky of a diagonal tile held in c (only j >= i is used and
 // written; the strict lower part is left as it is).  Pivots of rows >= nv are
 // padding (value 1).  The first failing pivot (<= 0 or NaN) is reported as
-// base + k + 1 into *info if *info is still 0.  The diagonal is sqrt(pivot)
-// and a row is scaled by the reciprocal of its diagonal, as in the element
-// recurrence.
+// base + k + 1 into *info if *info is still 0.  The diagonal is the square
+// root of the pivot and a row is scaled by the reciprocal of its diagonal, as
+// in the element recurrence (both from pivot_root).
 
 // Element schedule, right-looking: row k of the partly updated tile is final
 // after step k - 1; its owners publish it, and after one fence every lane
@@ -539,8 +562,8 @@ TLA_DI void tile_potf2_elem(Tile<T, TB>& c, lds_t<T>* buf, int nv, int base, lds
 #pragma unroll
     for (int r = 0; r < E; ++r) ri[r] = rowk[trow<T, TB>(l, r)];
     const int inf0 = *info;
-    const T d = sqrt(p);
-    const T rd = T(1) / d;
+    T d, rd;
+    pivot_root(p, d, rd);
     const T xj = rj * rd;
     if (l == 0 && !(p > T(0)) && k < nv && inf0 == 0) *info = base + k + 1;
     T pub = T(0);
@@ -601,8 +624,7 @@ TLA_DI void tile_potf2_strip(Tile<T, 16>& c, lds_t<T>* buf, int nv, int base, ld
 #pragma unroll
       for (int k = 0; k < p; ++k) piv -= x[k][p] * x[k][p];
       if (!(piv > T(0)) && o + p < nv && bad == 0) bad = base + o + p + 1;
-      x[p][p] = sqrt(piv);
-      rr[p] = T(1) / x[p][p];
+      pivot_root(piv, x[p][p], rr[p]);
 #pragma unroll
       for (int q = p + 1; q < 4; ++q) {
         T s = d[p][q];
