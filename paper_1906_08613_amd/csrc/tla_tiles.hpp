@@ -768,8 +768,31 @@ TLA_DI void tile_trsm_right_u_elem(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) 
 // 4g..4g+3 of vector v.  Block step G: strip G finishes with a 4 x 4 forward
 // substitution in registers and publishes; the strips below subtract
 // Xd^T(strip g, strip G) times it.  RIGHT selects rows of c as the vectors.
+// A coefficient tile outside LDS is first copied into the wave's scratch
+// (after the work tile) by one tile load whose element loads overlap; the
+// strips then read it from there instead of waiting on memory at each step.
+template <class V> struct InLds : std::false_type {};
+template <class T> struct InLds<View<T, true>> : std::true_type {};
+
+template <class T, class VX>
+TLA_DI View<T, true> stage_coef_tile(const VX& Xd, lds_t<T>* buf) {
+  constexpr int LD = 17;
+  lds_t<T>* Xs = buf + 16 * LD;
+  Tile<T, 16> xt;
+  tload(xt, Xd);
+  const int l = lane_id();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Xs[trow<T, 16>(l, r) + tcol<16>(l) * LD] = xt.v[r];
+  compiler_fence();
+  return View<T, true>{Xs, 1, LD};
+}
+
 template <class T, bool RIGHT, class VX>
 TLA_DI void tile_trsv_strips(Tile<T, 16>& c, const VX& Xd, lds_t<T>* buf) {
+  if constexpr (!InLds<VX>::value) {
+    tile_trsv_strips<T, RIGHT>(c, stage_coef_tile<T>(Xd, buf), buf);
+    return;
+  }
   const int l = lane_id(), jc = tcol<16>(l), g = l >> 4, v = l & 15;
   constexpr int LD = 17;
   constexpr int rs = RIGHT ? LD : 1, cs = RIGHT ? 1 : LD;  // element e of vector v at e*rs + v*cs
@@ -831,6 +854,10 @@ TLA_DI void tile_trsv_strips(Tile<T, 16>& c, const VX& Xd, lds_t<T>* buf) {
 // subtract Xd(strip g, strip G) times the finished strip.
 template <class T, class VX>
 TLA_DI void tile_trsm_u(Tile<T, 16>& c, const VX& Xd, lds_t<T>* buf) {
+  if constexpr (!InLds<VX>::value) {
+    tile_trsm_u<T>(c, stage_coef_tile<T>(Xd, buf), buf);
+    return;
+  }
   const int l = lane_id(), jc = tcol<16>(l), g = l >> 4, v = l & 15;
   constexpr int LD = 17;
   lds_t<T>* S = buf;
