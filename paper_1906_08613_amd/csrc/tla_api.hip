@@ -74,27 +74,25 @@ bool candidate(int op, int i, tla_plan* p) {
 }
 
 // The plan used without a tuning table: 16 x 16 matrix-core tiles, the
-// tile-wavefront / right-looking variant (left-looking for the Cholesky
-// factorisation of the large sizes, where it measured 1.4x faster), and the
-// placement that measured best at n = 64 (FP64 above n = 32 in place in
-// global memory, except Cholesky, whose factor stays in LDS up to n = 64;
-// mixed above n = 32 with the FP64 solution in the workspace).
+// tile-wavefront variant for the Sylvester and Lyapunov equations, and what
+// measured best at n = 32, 64 and 128 otherwise.  FP64: in place in global
+// memory, one wave per instance up to n = 64 (two or four above), bordered
+// Cholesky (left-looking for the large sizes, where it measured 1.4x faster
+// than right-looking).  Mixed: above n = 32 with the FP64 solution in the
+// workspace.
 tla_plan default_plan(int op, int n, int prec) {
   tla_plan p;
   p.variant = (op == TLA_POTRF && n > kMaxN) ? 1 : 0;
   p.tile = 16;
   p.engine = 1;
-  if (n <= 32) {
+  if (prec == TLA_F64) {
+    // in place, one wave per instance up to n = 64 (bordered Cholesky)
+    if (op == TLA_POTRF && n <= kMaxN) p.variant = 2;
+    p.waves = (op == TLA_POTRF || n <= 64) ? 1 : (op == TLA_TRSYL ? 4 : 2);
+    p.place = 3;
+  } else if (n <= 32) {
     p.waves = n <= 16 ? 1 : 2;
     p.place = 0;
-  } else if (prec == TLA_F64) {
-    if (op == TLA_POTRF && n <= 64) {
-      p.waves = 4;
-      p.place = 0;
-    } else {
-      p.waves = op == TLA_TRSYL ? 1 : 2;
-      p.place = 3;
-    }
   } else {
     p.waves = op == TLA_POTRF ? 4 : 2;
     p.place = 2;
