@@ -4,18 +4,28 @@
 
 namespace tla {
 
+// One-wave in-place kernels (placement 3 of the sizes up to 128) are held to
+// the register budget of 4 (Cholesky) or 5 (tile-wavefront Sylvester and
+// Lyapunov) resident waves per SIMD: at n = 64 that measured 10% (Cholesky)
+// and 2-3% (Sylvester) faster than the compiler's own choice of 3 or 4.  The
+// other Sylvester and Lyapunov variants would spill at that budget.
+template <int NW>
+constexpr int kInplaceWavesChol = NW == 1 ? 4 : 1;
 template <int NW, int VAR>
-__global__ __launch_bounds__(NW * 64) void k_potrf_large(KArgs g) {
+constexpr int kInplaceWaves = NW == 1 && VAR == 0 ? 5 : 1;
+
+template <int NW, int VAR>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(kInplaceWavesChol<NW>))) void k_potrf_large(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   potrf_inplace_body<NW, VAR>(g, fetch_uniform(g, blockIdx.x), smem);
 }
 template <int NW, int VAR>
-__global__ __launch_bounds__(NW * 64) void k_trsyl_large(KArgs g) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(kInplaceWaves<NW, VAR>))) void k_trsyl_large(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   trsyl_inplace_body<NW, VAR>(g, fetch_uniform(g, blockIdx.x), smem);
 }
 template <int NW, int VAR>
-__global__ __launch_bounds__(NW * 64) void k_trlyap_large(KArgs g) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(kInplaceWaves<NW, VAR>))) void k_trlyap_large(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   trlyap_inplace_body<NW, VAR>(g, fetch_uniform(g, blockIdx.x), smem);
 }

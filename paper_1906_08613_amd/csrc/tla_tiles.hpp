@@ -80,6 +80,10 @@ struct View {
     if constexpr (!LDS) __threadfence_block();
   }
 };
+// True for views of matrices in LDS.
+template <class V> struct InLds : std::false_type {};
+template <class T> struct InLds<View<T, true>> : std::true_type {};
+
 template <class T>
 TLA_DI View<T, true> colmajor(T* p, int ld) { return View<T, true>{to_lds(p), 1, ld}; }
 template <class T>
@@ -494,15 +498,49 @@ struct ViewPair {
   VU U;
 };
 
+// Coefficient tiles outside LDS are fetched as two whole tiles (their loads
+// read along columns) instead of the 14 gathered elements per lane of the 2 x 2
+// block schedule, and staged through the wave's scratch when the solve starts.
+template <class T>
+struct Blk2Tiles {
+  Tile<T, 16> L, U;
+};
+
+template <class T>
+TLA_DI Blk2Coef<T> blk2_from_tiles(const Blk2Tiles<T>& t, lds_t<T>* buf) {
+  constexpr int LD = 17;
+  lds_t<T>* Ls = buf;
+  lds_t<T>* Us = buf + 16 * LD;
+  const int l = lane_id(), j = tcol<16>(l);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    Ls[trow<T, 16>(l, r) + j * LD] = t.L.v[r];
+    Us[trow<T, 16>(l, r) + j * LD] = t.U.v[r];
+  }
+  compiler_fence();
+  const Blk2Coef<T> k = blk2_fetch<T>(View<T, true>{Ls, 1, LD}, View<T, true>{Us, 1, LD});
+  compiler_fence();  // served before the solver's first writes to the scratch
+  return k;
+}
+
 template <class T, int TB, class VL, class VU>
 TLA_DI auto sylv_fetch(const VL& Lt, const VU& Ut) {
-  if constexpr (TB == 16) return blk2_fetch<T>(Lt, Ut);
-  else return ViewPair<VL, VU>{Lt, Ut};
+  if constexpr (TB == 16 && InLds<VL>::value && InLds<VU>::value) {
+    return blk2_fetch<T>(Lt, Ut);
+  } else if constexpr (TB == 16) {
+    Blk2Tiles<T> t;
+    tload(t.L, Lt);
+    tload(t.U, Ut);
+    return t;
+  } else {
+    return ViewPair<VL, VU>{Lt, Ut};
+  }
 }
 
 template <class T, int TB, class K>
 TLA_DI void sylv_solve(Tile<T, TB>& c, const K& k, lds_t<T>* buf, int ni, int nj) {
-  if constexpr (TB == 16) tile_sylv_blk2<T>(c, k, buf, ni, nj);
+  if constexpr (TB == 16 && std::is_same_v<K, Blk2Tiles<T>>) tile_sylv_blk2<T>(c, blk2_from_tiles<T>(k, buf), buf, ni, nj);
+  else if constexpr (TB == 16) tile_sylv_blk2<T>(c, k, buf, ni, nj);
   else tile_sylv_elem<T, TB>(c, k.L, k.U, buf, ni, nj);
 }
 
@@ -771,9 +809,6 @@ TLA_DI void tile_trsm_right_u_elem(Tile<T, TB>& c, const VX& Xd, lds_t<T>* buf) 
 // A coefficient tile outside LDS is first copied into the wave's scratch
 // (after the work tile) by one tile load whose element loads overlap; the
 // strips then read it from there instead of waiting on memory at each step.
-template <class V> struct InLds : std::false_type {};
-template <class T> struct InLds<View<T, true>> : std::true_type {};
-
 template <class T, class VX>
 TLA_DI View<T, true> stage_coef_tile(const VX& Xd, lds_t<T>* buf) {
   constexpr int LD = 17;
