@@ -186,7 +186,10 @@ namespace tla {
 size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int pl) {
   const size_t np = (size_t)ntmax * tb;
   const size_t mat8 = np * (np + 1) * 8, mat4 = np * (np + 1) * 4;
-  const size_t scr = (size_t)nw * wave_scratch(tb) * 8 + 16 + 8 * (nw + 4);
+  // tile solvers' scratch (FP32 elements for the mixed kernels whose FP64
+  // fallback is a second launch), alignment, reduction cells
+  const size_t scr_elem = (prec != TLA_F64 && pl >= 2) ? 4 : 8;
+  const size_t scr = (size_t)nw * wave_scratch(tb) * scr_elem + 16 + 8 * (nw + 4);
   if (prec == TLA_F64) {
     if (pl == 3) return inplace_lds_bytes(nw);
     if (op == TLA_POTRF) return mat8 + scr;

@@ -114,13 +114,21 @@ TLA_DI MixedLds carve(unsigned char* smem, const KArgs& g, int naux) {
     m.A2 = m.A1 + (naux >= 1 ? mat : 0);
     after = m.A2 + (naux >= 2 ? mat : 0);
   }
-  // scratch sized for FP64 (the fallback solve reuses it), 8-byte aligned
+  // tile solvers' scratch, 8-byte aligned: FP32 elements when the FP64
+  // fallback is a second launch (XG), else FP64 (the fallback solve reuses it)
   m.wb = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(after) + 7) & ~uintptr_t(7));
-  m.red = reinterpret_cast<double*>(m.wb) + NW * wave_scratch(TB);
+  m.red = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(m.wb) +
+                                    (size_t)NW * wave_scratch(TB) * (XG ? sizeof(float) : sizeof(double)));
   m.ired = reinterpret_cast<int*>(m.red + NW + 1);
   m.info = m.ired + 1;
   return m;
 }
+
+// Two-wave Sylvester and Lyapunov kernels with the FP64 solution in the
+// workspace fit 7 instances per compute unit in LDS; their registers are held
+// to 4 resident waves per SIMD to match (the compiler alone allows 3).
+template <int NW, bool XG, bool WG>
+constexpr int kMixedWaves = (NW == 2 && XG && !WG) ? 4 : 1;
 
 // True when every entry of the n x n leading block is finite (work matrix in
 // LDS, or in global memory for !LDS).
@@ -260,7 +268,7 @@ TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
 }
 
 template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG, bool WG = false>
-__global__ __launch_bounds__(NW * 64) void k_trsyl_mixed(KArgs g) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(kMixedWaves<NW, XG, WG>))) void k_trsyl_mixed(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   trsyl_mixed_body<TB, ENG, NW, VAR, LU_LDS, XG, WG>(g, fetch_uniform(g, blockIdx.x), smem);
 }
@@ -374,7 +382,7 @@ TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* sme
 }
 
 template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG, bool WG = false>
-__global__ __launch_bounds__(NW * 64) void k_trlyap_mixed(KArgs g) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(kMixedWaves<NW, XG, WG>))) void k_trlyap_mixed(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   trlyap_mixed_body<TB, ENG, NW, VAR, LU_LDS, XG, WG>(g, fetch_uniform(g, blockIdx.x), smem);
 }
