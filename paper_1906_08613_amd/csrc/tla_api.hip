@@ -197,7 +197,7 @@ size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int pl) {
     return mat8 * (pl == 0 ? 2 : 1) + scr;
   }
   if (pl == 3) return scr;
-  if (op == TLA_POTRF) return (pl == 0 ? mat8 : 0) + 2 * mat4 + scr;
+  if (op == TLA_POTRF) return (pl == 0 ? mat8 + 2 * mat4 : mat4) + scr;  // place 2: factor copy in the workspace
   const size_t coef = pl == 0 ? (op == TLA_TRSYL ? 2 : 1) * mat4 : 0;
   return (pl == 2 ? 0 : mat8) + mat4 + coef + scr;
 }
@@ -272,7 +272,7 @@ static tla_status launch_one(tla_ctx* h, KFn fn, size_t lds, int grid, int waves
 // there (placement 2), or the FP32 work matrices too (placement 3, large n).
 static long long work_stride(int pl, int ntmax) {
   const long long np = (long long)ntmax * 16, mat = np * (np + 1);
-  return pl == 3 ? 2 * mat : mat;
+  return pl == 3 ? 2 * mat : (3 * mat + 1) / 2;  // place 2: solution + an FP32 matrix
 }
 
 static tla_status ensure_work(tla_ctx* h, KArgs& a, int pl) {

@@ -85,8 +85,9 @@ struct MixedLds {
 };
 
 // With XG the FP64 solution lives in a global workspace slot instead (sizes
-// where it does not fit next to W); every access to it is then separated by
-// workgroup barriers, and the FP64 fallback runs as a second launch.  With WG
+// where it does not fit next to W), followed there by the FP32 auxiliary
+// matrices; every access to them is separated by workgroup barriers, and the
+// FP64 fallback runs as a second launch.  With WG
 // (which implies XG) the FP32 work matrix and the FP32 auxiliary matrices
 // follow it into the slot, after the solution, and LDS keeps only the tile
 // solvers' scratch and the reduction cells.
@@ -104,15 +105,20 @@ TLA_DI MixedLds carve(unsigned char* smem, const KArgs& g, int naux) {
     after = reinterpret_cast<float*>(smem);
   } else {
     if constexpr (XG) {
+      // the FP32 auxiliary matrices (the Cholesky factor copy) follow the
+      // solution into the workspace; LDS keeps the work matrix
       m.Xd = g.work + (size_t)blockIdx.x * g.work_stride;
       m.W = reinterpret_cast<float*>(smem);
+      m.A1 = reinterpret_cast<float*>(m.Xd + mat);
+      m.A2 = m.A1 + (naux >= 1 ? mat : 0);
+      after = m.W + mat;
     } else {
       m.Xd = reinterpret_cast<double*>(smem);
       m.W = reinterpret_cast<float*>(m.Xd + mat);
+      m.A1 = m.W + mat;
+      m.A2 = m.A1 + (naux >= 1 ? mat : 0);
+      after = m.A2 + (naux >= 2 ? mat : 0);
     }
-    m.A1 = m.W + mat;
-    m.A2 = m.A1 + (naux >= 1 ? mat : 0);
-    after = m.A2 + (naux >= 2 ? mat : 0);
   }
   // tile solvers' scratch, 8-byte aligned: FP32 elements when the FP64
   // fallback is a second launch (XG), else FP64 (the fallback solve reuses it)
@@ -173,6 +179,7 @@ TLA_DI void egress_sym_tiles(double* Gg, int ldg, int n, const double* Xg, int l
 // ===================================================== Sylvester, mixed
 template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG, bool WG = false>
 TLA_DI void trsyl_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem) {
+  static_assert(!(LU_LDS && XG), "coefficients in LDS only with the solution in LDS");
   int n;
   if (!validate(in, g.n_max, n)) return;
   const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
@@ -276,6 +283,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(kMixedW
 // ===================================================== Lyapunov, mixed
 template <int TB, int ENG, int NW, int VAR, bool LU_LDS, bool XG, bool WG = false>
 TLA_DI void trlyap_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem) {
+  static_assert(!(LU_LDS && XG), "coefficients in LDS only with the solution in LDS");
   int n;
   if (!validate(in, g.n_max, n)) return;
   const int nt = (n + TB - 1) / TB, np = nt * TB, ld = np + 1;
@@ -391,8 +399,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(kMixedW
 // Tile solves of the Newton correction, FP32 (X32 upper factor in aux):
 //   M1 = X^{-T} R   column tile by column tile (forward substitution down)
 //   M  = M1 X^{-1}  row tile by row tile (substitution to the right)
-template <class T, int TB, int ENG, int NW, class VW, class VXd>
-TLA_DI void newton_correction(const VW& Wv, const VW& Xv, const VXd& Xd, int nt, lds_t<T>* wbuf) {
+template <class T, int TB, int ENG, int NW, class VW, class VF, class VXd>
+TLA_DI void newton_correction(const VW& Wv, const VF& Xv, const VXd& Xd, int nt, lds_t<T>* wbuf) {
   typedef Gemm<T, TB, ENG> G;
   const int w = wave_id();
   for (int J = w; J < nt; J += NW) {
@@ -496,7 +504,7 @@ TLA_DI void potrf_mixed_body(const KArgs& g, const Inst& in, unsigned char* smem
         m.A1[i + j * ld] = i < n && j < n ? float(m.Xd[i + j * ld]) : (i == j ? 1.0f : 0.0f);
       }
       __syncthreads();
-      newton_correction<float, TB, ENG, NW>(xcolmajor<WG>(m.W, ld), xcolmajor<WG>(m.A1, ld), Xv, nt, to_lds(m.wb + wave_id() * wave_scratch(TB)));
+      newton_correction<float, TB, ENG, NW>(xcolmajor<WG>(m.W, ld), xcolmajor<XG>(m.A1, ld), Xv, nt, to_lds(m.wb + wave_id() * wave_scratch(TB)));
       ++st.it;
       __syncthreads();
     }

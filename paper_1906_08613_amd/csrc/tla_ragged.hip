@@ -346,7 +346,7 @@ static tla_status rag_plan(tla_ctx* h, int prec, int batch, int n_max, tla_stat*
       L.grid = std::min(h->num_cu * occ, batch);
       if (eff_prec != TLA_F64 && cfg.pl == 2) {
         const size_t np = (size_t)g.ntmax * 16;
-        g.work_stride = (long long)(np * (np + 1));
+        g.work_stride = (long long)((3 * np * (np + 1) + 1) / 2);
         if ((size_t)L.grid * g.work_stride * sizeof(double) > h->work_bytes) return TLA_E_NOMEM;
         g.work = h->work;
       }
@@ -409,7 +409,7 @@ extern "C" tla_status tla_ragged_batched(tla_handle h, tla_prec prec, int batch,
   tla_stat* st = stat;
   if (prec != TLA_F64) {
     // workspace for the FP64 solutions of the largest class (one slot per persistent workgroup)
-    const size_t np = 128, slot = np * (np + 1) * sizeof(double);
+    const size_t np = 128, slot = (3 * np * (np + 1) + 1) / 2 * sizeof(double);  // solution + an FP32 matrix
     const size_t need = (size_t)h->num_cu * 8 * slot;
     if (need > h->work_bytes || (!stat && (size_t)batch > h->stat_cap)) {
       hipStreamSynchronize(h->stream);
