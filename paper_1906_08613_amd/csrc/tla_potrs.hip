@@ -39,7 +39,7 @@ struct RectView {
 };
 
 template <int NW>
-__global__ __launch_bounds__(NW * 64) void k_potrs(KArgs g) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_potrs(KArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x;
   const int n = g.n[b], m = g.m[b];
