@@ -161,8 +161,9 @@ tla_status tla_ragged_batched(tla_handle h, tla_prec prec, int batch, int n_max,
  * place   = 0 stage the triangular coefficients in LDS when they fit,
  *           1 read them through the caches (smaller LDS footprint, more
  *           instances per compute unit; Sylvester and Lyapunov only),
- *           2 (mixed precisions only) also keep the FP64 solution in the
- *           handle's workspace; its FP64 fallback is then a second launch,
+ *           2 (mixed precisions only) also keep the FP64 solution (and,
+ *           for the Cholesky factorisation, the FP32 copy of the factor) in
+ *           the handle's workspace; its FP64 fallback is then a second launch,
  *           3 (FP64 only; tile 16 with the matrix cores) solve in place in
  *           the caller's matrices in global memory, only the tile solvers'
  *           scratch in LDS (the most instances per compute unit).
