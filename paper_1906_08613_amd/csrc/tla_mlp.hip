@@ -4,7 +4,7 @@
 // loops as future work (Limitations and future work paragraph); here the
 // network is trained on the autotuner's own measurements, on the GPU, by the
 // forward, backward and Adam kernels below, and the measured table stays the
-// fallback and the judge of its picks.
+// fallback and the reference its picks are measured against.
 //
 // Network: in (kMlpIn features) -> 64 ReLU -> 64 ReLU -> 1, FP32, loss
 // = mean squared error on standardised log seconds.  Parameters are one flat

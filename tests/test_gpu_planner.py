@@ -105,7 +105,7 @@ def test_mlp_learns_synthetic_costs(h, tmp_path):
 
 def test_mlp_regret_on_measured_timings(h, tmp_path):
     # measured autotuner table at n = 8..128 step 8 (f64); the network is
-    # trained without the held-out sizes 56 and 112 and judged on them
+    # trained without the held-out sizes 56 and 112 and evaluated on them
     ns = list(range(8, 129, 8))
     ht = tla.Handle(0)
     ht.tune(["potrf", "trsyl", "trlyap"], ns, ["f64"], batch=512, reps=2)
