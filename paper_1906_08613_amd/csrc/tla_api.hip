@@ -171,6 +171,7 @@ extern "C" tla_status tla_set_refine(tla_handle h, double tau, int max_iter) {
   if (!h || !(tau >= 0.0) || max_iter < 0) return TLA_E_ARG;
   h->tau = tau;
   h->max_iter = max_iter;
+  ++h->gen;
   return TLA_OK;
 }
 
@@ -202,10 +203,15 @@ size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int pl) {
   return (pl == 2 ? 0 : mat8) + mat4 + coef + scr;
 }
 
+// Grows the handle's workspace and refinement-record buffers.  A buffer is
+// freed only after the whole device has finished (work on an earlier stream
+// of the handle may still use it), and every reallocation bumps the handle's
+// generation so that no cached ragged graph replays with the old address.
 static tla_status ensure_buffers(tla_ctx* h, size_t work_bytes, int batch) {
   if (work_bytes > h->work_bytes) {
+    ++h->gen;
     if (h->work) {
-      hipStreamSynchronize(h->stream);
+      hipDeviceSynchronize();
       hipFree(h->work);
       h->work = nullptr;
       h->work_bytes = 0;
@@ -214,8 +220,9 @@ static tla_status ensure_buffers(tla_ctx* h, size_t work_bytes, int batch) {
     h->work_bytes = work_bytes;
   }
   if ((size_t)batch > h->stat_cap) {
+    ++h->gen;
     if (h->stat_buf) {
-      hipStreamSynchronize(h->stream);
+      hipDeviceSynchronize();
       hipFree(h->stat_buf);
       h->stat_buf = nullptr;
       h->stat_cap = 0;
@@ -494,5 +501,6 @@ extern "C" const char* tla_variant_name(tla_op op, int variant) {
 extern "C" tla_status tla_set_picker(tla_handle h, tla_picker mode) {
   if (!h || mode < TLA_PICK_DEFAULT || mode > TLA_PICK_MLP) return TLA_E_ARG;
   h->picker = mode;
+  ++h->gen;
   return TLA_OK;
 }

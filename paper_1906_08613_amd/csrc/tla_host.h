@@ -42,6 +42,11 @@ struct tla_ctx {
   size_t work_bytes = 0;
   tla_stat* stat_buf = nullptr;                   // refinement records when the caller passes none
   size_t stat_cap = 0;
+  // Bumped whenever something a captured ragged graph has baked in changes:
+  // the workspace or refinement-record buffers are reallocated, the
+  // refinement settings change, or the tuning table / picker changes.
+  // Cached graphs from an older generation are dropped before any replay.
+  unsigned long long gen = 0;
   void release();
 };
 

@@ -276,6 +276,7 @@ namespace tla {
 struct RagState {
   RagBuffers buf;
   hipStream_t cap_stream = nullptr;
+  unsigned long long gen = 0;  // handle generation the cached graphs were captured in
   struct Entry {
     const void* d;
     int batch, n_max, prec;
@@ -308,8 +309,15 @@ struct RagLaunch {
 
 // Host-side part: per class and pass, the kernel, grid and LDS (queries that
 // must not run while a stream is being captured).
-static tla_status rag_plan(tla_ctx* h, int prec, int batch, int n_max, tla_stat* stat, std::vector<RagLaunch>& out) {
-  out.clear();
+static void rag_drop_graphs(RagState* s) {
+  for (auto& e : s->graphs) { hipGraphExecDestroy(e.exec); hipGraphDestroy(e.graph); }
+  s->graphs.clear();
+}
+
+constexpr int kRagMaxLaunches = 2 * kRagClasses;  // class workers of the first pass and the FP64 second pass
+
+static tla_status rag_plan(tla_ctx* h, int prec, int batch, int n_max, tla_stat* stat, RagLaunch* out, int* nout) {
+  *nout = 0;
   for (int pass = 0; pass < (prec == TLA_F64 ? 1 : 2); ++pass) {
     for (int cls = kRagClasses - 1; cls >= 0; --cls) {
       if (n_max <= (cls == 0 ? 0 : kRagClassMax[cls - 1])) continue;  // class cannot occur
@@ -359,23 +367,24 @@ static tla_status rag_plan(tla_ctx* h, int prec, int batch, int n_max, tla_stat*
         if ((size_t)L.grid * g.work_stride * sizeof(double) > h->work_bytes) return TLA_E_NOMEM;
         g.work = h->work;
       }
-      out.push_back(L);
+      out[(*nout)++] = L;
     }
   }
   return TLA_OK;
 }
 
-static tla_status rag_enqueue(tla_ctx* h, hipStream_t st, int batch, int n_max, const tla_desc* d, int* info,
-                              tla_stat* stat, const std::vector<RagLaunch>& plan) {
-  RagState* s = h->rag;
-  RagArgs r{d, batch, n_max, info, stat, s->buf.rank, s->buf.keycount, s->buf.keyoff, s->buf.queue, s->buf.cls};
-  const int tpb = 256, blocks = (batch + tpb - 1) / tpb;
+// Enqueues the work-list preparation and the class workers; r holds the
+// work-list buffers (the handle's, or the allocation-free entry point's).
+static tla_status rag_enqueue(hipStream_t st, const RagArgs& r, const RagLaunch* plan, int nplan) {
+  const int tpb = 256, blocks = (r.batch + tpb - 1) / tpb;
   hipLaunchKernelGGL(k_rag_zero, dim3(8), dim3(256), 0, st, r);
   hipLaunchKernelGGL(k_rag_hist, dim3(blocks), dim3(tpb), 0, st, r);
   hipLaunchKernelGGL(k_rag_scan, dim3(1), dim3(256), 0, st, r);
   hipLaunchKernelGGL(k_rag_scatter, dim3(blocks), dim3(tpb), 0, st, r);
-  for (const RagLaunch& L : plan)
+  for (int i = 0; i < nplan; ++i) {
+    const RagLaunch& L = plan[i];
     hipLaunchKernelGGL(L.fn, dim3(L.grid), dim3(64 * L.waves), L.lds, st, r, L.g, L.rv, L.cls, L.slot);
+  }
   return hipGetLastError() == hipSuccess ? TLA_OK : TLA_E_HIP;
 }
 
@@ -393,15 +402,12 @@ extern "C" tla_status tla_ragged_batched(tla_handle h, tla_prec prec, int batch,
     if (hipStreamCreateWithFlags(&h->rag->cap_stream, hipStreamNonBlocking) != hipSuccess) return TLA_E_HIP;
   }
   RagState* s = h->rag;
-  bool regrow = false;
   if (batch > s->buf.cap) {
-    hipStreamSynchronize(h->stream);
-    for (auto& e : s->graphs) { hipGraphExecDestroy(e.exec); hipGraphDestroy(e.graph); }
-    s->graphs.clear();
+    hipDeviceSynchronize();
+    rag_drop_graphs(s);
     hipFree(s->buf.queue);
     if (hipMalloc(&s->buf.queue, (size_t)batch * sizeof(int)) != hipSuccess) return TLA_E_NOMEM;
     s->buf.cap = batch;
-    regrow = true;
   }
   if (!s->buf.rank) {
     std::vector<int> rank = cost_rank();
@@ -413,7 +419,6 @@ extern "C" tla_status tla_ragged_batched(tla_handle h, tla_prec prec, int batch,
     if (hipMemcpy(s->buf.rank, rank.data(), rank.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
       return TLA_E_HIP;
   }
-  (void)regrow;
   // the mixed second pass reads refinement records: use the handle's when none given
   tla_stat* st = stat;
   if (prec != TLA_F64) {
@@ -421,9 +426,8 @@ extern "C" tla_status tla_ragged_batched(tla_handle h, tla_prec prec, int batch,
     const size_t np = 128, slot = (3 * np * (np + 1) + 1) / 2 * sizeof(double);  // solution + an FP32 matrix
     const size_t need = (size_t)h->num_cu * 8 * slot;
     if (need > h->work_bytes || (!stat && (size_t)batch > h->stat_cap)) {
-      hipStreamSynchronize(h->stream);
-      for (auto& e : s->graphs) { hipGraphExecDestroy(e.exec); hipGraphDestroy(e.graph); }
-      s->graphs.clear();
+      hipDeviceSynchronize();
+      ++h->gen;
       if (need > h->work_bytes) {
         hipFree(h->work);
         h->work = nullptr;
@@ -441,20 +445,28 @@ extern "C" tla_status tla_ragged_batched(tla_handle h, tla_prec prec, int batch,
     }
     if (!st) st = h->stat_buf;
   }
+  // graphs captured before a workspace reallocation, a refinement-setting
+  // change or a tuning-table change hold stale pointers or parameters
+  if (s->gen != h->gen) {
+    rag_drop_graphs(s);
+    s->gen = h->gen;
+  }
   for (auto& e : s->graphs) {
     if (e.d == d && e.batch == batch && e.n_max == n_max && e.prec == prec && e.info == info && e.stat == st &&
         e.stream == (void*)h->stream) {
       return hipGraphLaunch(e.exec, h->stream) == hipSuccess ? TLA_OK : TLA_E_HIP;
     }
   }
-  std::vector<RagLaunch> plan;
-  tla_status ps = rag_plan(h, prec, batch, n_max, st, plan);
+  RagLaunch plan[kRagMaxLaunches];
+  int nplan = 0;
+  tla_status ps = rag_plan(h, prec, batch, n_max, st, plan, &nplan);
   if (ps != TLA_OK) return ps;
-  if (getenv("TLA_NO_GRAPH")) return rag_enqueue(h, h->stream, batch, n_max, d, info, st, plan);
+  const RagArgs r{d, batch, n_max, info, st, s->buf.rank, s->buf.keycount, s->buf.keyoff, s->buf.queue, s->buf.cls};
+  if (getenv("TLA_NO_GRAPH")) return rag_enqueue(h->stream, r, plan, nplan);
   // capture the whole sequence once; later calls replay it
   hipGraph_t graph = nullptr;
   if (hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return TLA_E_HIP;
-  tla_status rs = rag_enqueue(h, s->cap_stream, batch, n_max, d, info, st, plan);
+  tla_status rs = rag_enqueue(s->cap_stream, r, plan, nplan);
   hipError_t ce = hipStreamEndCapture(s->cap_stream, &graph);
   if (rs != TLA_OK) { if (graph) hipGraphDestroy(graph); return rs; }
   if (ce != hipSuccess) return TLA_E_HIP;

@@ -185,6 +185,7 @@ extern "C" tla_status tla_tune(tla_handle h, int n_ops, const int* ops, int n_ns
       }
     }
   }
+  ++h->gen;  // the table changed: cached ragged graphs hold the old variants
   return TLA_OK;
 }
 
@@ -240,6 +241,7 @@ extern "C" tla_status tla_load_table(tla_handle h, const char* path) {
     if (it == bt.end() || r.seconds < it->second) { bt[k] = r.seconds; h->best[k] = r.plan; }
   }
   fclose(f);
+  ++h->gen;
   return TLA_OK;
 }
 

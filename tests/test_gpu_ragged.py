@@ -165,3 +165,54 @@ def test_ragged_maps_uncompiled_variants_to_wavefront(h, tmp_path):
     for b in range(rb_t.batch):
         assert np.array_equal(rb_t.result(b), rb_d.result(b)), (b, ops[b], ns[b])
     h2.close()
+
+
+def test_ragged_graph_after_workspace_regrowth(orc):
+    # A captured ragged graph bakes in the handle's workspace address.  A
+    # larger uniform mixed call reallocates that workspace; the next ragged
+    # call with the same arguments must not replay the old graph (it would
+    # write freed memory) but capture a new one: its results still match the
+    # oracle.  A refinement-setting change likewise forces a new capture.
+    hd = tla.Handle(0)
+    hd.set_picker(tla.PICK_DEFAULT)
+    ops, ns, mats = make_batch("regrow", 96)
+    rb = tla.RaggedBatch(ops, mats)
+    pristine = rb.buf.clone()
+
+    def check_ragged(tag):
+        torch.cuda.synchronize()
+        assert np.all(rb.info.cpu().numpy() == 0), tag
+        for b in range(rb.batch):
+            X = rb.result(b)
+            if ops[b] == 0:
+                X = np.triu(X)
+            assert eta_one(orc, ops[b], mats[b], X) <= 1e-12, (tag, b, ops[b], ns[b])
+
+    tla.ragged(hd, rb, "mixed_f32")              # captures, small workspace
+    check_ragged("first")
+    # uniform mixed Cholesky at n = 128 over 8192 instances: its workspace
+    # (FP64 solution and an FP32 matrix per instance) is larger than the
+    # ragged call's, so the handle reallocates it
+    n, batch = 128, 8192
+    g = torch.Generator(device="cuda").manual_seed(7)
+    B = torch.rand((batch, n, n), generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+    A = B.transpose(1, 2).contiguous() @ B + n * torch.eye(n, device="cuda", dtype=torch.float64)
+    A0 = A[:4].cpu().numpy()                     # symmetric: [b, j, i] == [b, i, j]
+    Ad = A.contiguous()
+    o = tla.potrf(hd, Ad, "mixed_f32")
+    torch.cuda.synchronize()
+    assert np.all(o.info.cpu().numpy() == 0)
+    Xg = np.triu(tla.from_device_cm(Ad[:4]))
+    for b in range(4):
+        assert orc.eta_potrf(A0[b], Xg[b]) <= 1e-12, b
+    del A, B, Ad
+    rb.buf.copy_(pristine)
+    rb.info.zero_()
+    tla.ragged(hd, rb, "mixed_f32")              # same arguments: must recapture
+    check_ragged("after regrowth")
+    rb.buf.copy_(pristine)
+    rb.info.zero_()
+    hd.set_refine(1e-13, 6)                      # new refinement settings: recapture
+    tla.ragged(hd, rb, "mixed_f32")
+    check_ragged("after set_refine")
+    hd.close()
