@@ -146,6 +146,24 @@ tla_status tla_potrs_batched(tla_handle h, int batch, int n_max, const int *n, i
 tla_status tla_potri_batched(tla_handle h, int batch, int n_max, const int *n, const double *const *X,
                              const int *ldx, double *const *Y, const int *ldy, int *info);
 
+/* FP32-I/O twins of the three batched solves (paper Fig. 2a, 2c, 2b): the
+ * same operations, argument roles, layouts, referenced triangles, in-place
+ * semantics and info codes as tla_potrf_batched, tla_trsyl_batched and
+ * tla_trlyap_batched, on single-precision matrices (float*), computed in
+ * single precision (FP32 vector arithmetic for the diagonal tiles, FP32
+ * matrix cores for the tile updates).  No refinement and no stat record:
+ * the result carries FP32 rounding errors (backward error of order n times
+ * the FP32 unit roundoff).  0 <= n[b] <= n_max <= 4096.  All arrays
+ * (pointer arrays included) are device memory owned by the caller.
+ * Asynchronous on the handle's stream. */
+tla_status tla_spotrf_batched(tla_handle h, int batch, int n_max, const int *n, float *const *A, const int *lda,
+                              int *info);
+tla_status tla_strsyl_batched(tla_handle h, int batch, int n_max, const int *n, const float *const *L,
+                              const int *ldl, const float *const *U, const int *ldu, float *const *C,
+                              const int *ldc, int *info);
+tla_status tla_strlyap_batched(tla_handle h, int batch, int n_max, const int *n, const float *const *L,
+                               const int *ldl, float *const *S, const int *lds, int *info);
+
 /* Mixed batch of all three operations and uneven n in one persistent launch
  * (captured as a HIP graph and replayed when the same descriptor array, batch
  * and precision come again).  d: tla_desc[batch]. */

@@ -32,7 +32,8 @@ OPS = {"potrf": POTRF, "trsyl": TRSYL, "trlyap": TRLYAP}
 SYMBOLS = [
     "tla_create", "tla_destroy", "tla_set_stream", "tla_sync",
     "tla_potrf_batched", "tla_trsyl_batched", "tla_trlyap_batched", "tla_ragged_batched",
-    "tla_potrs_batched", "tla_potri_batched", "tla_set_plan", "tla_get_plan", "tla_num_candidates", "tla_candidate", "tla_variant_name",
+    "tla_potrs_batched", "tla_potri_batched",
+    "tla_spotrf_batched", "tla_strsyl_batched", "tla_strlyap_batched", "tla_set_plan", "tla_get_plan", "tla_num_candidates", "tla_candidate", "tla_variant_name",
     "tla_tune", "tla_time_plan", "tla_save_table", "tla_load_table", "tla_set_picker",
     "tla_set_refine", "tla_status_string",
     "tla_mlp_num_params", "tla_mlp_num_features", "tla_mlp_features", "tla_mlp_set_params",
@@ -92,6 +93,9 @@ def lib():
             "tla_ragged_batched": (I, [V, I, I, I, P, P, P]),
             "tla_potrs_batched": (I, [V, I, I, P, I, P, P, P, P, P, P]),
             "tla_potri_batched": (I, [V, I, I, P, P, P, P, P, P]),
+            "tla_spotrf_batched": (I, [V, I, I, P, P, P, P]),
+            "tla_strsyl_batched": (I, [V, I, I, P, P, P, P, P, P, P, P]),
+            "tla_strlyap_batched": (I, [V, I, I, P, P, P, P, P, P]),
             "tla_set_plan": (I, [V, I, I, ctypes.POINTER(Plan)]),
             "tla_get_plan": (I, [V, I, I, I, I, ctypes.POINTER(Plan)]),
             "tla_num_candidates": (I, [I]),
@@ -191,6 +195,18 @@ class Handle:
     def potri_batched(self, batch, n_max, n, X, ldx, Y, ldy, info):
         check(lib().tla_potri_batched(self.h, batch, n_max, _ptr(n), _ptr(X), _ptr(ldx), _ptr(Y), _ptr(ldy),
                                       _ptr(info)), "tla_potri_batched")
+
+    def spotrf_batched(self, batch, n_max, n, A, lda, info):
+        check(lib().tla_spotrf_batched(self.h, batch, n_max, _ptr(n), _ptr(A), _ptr(lda), _ptr(info)),
+              "tla_spotrf_batched")
+
+    def strsyl_batched(self, batch, n_max, n, L, ldl, U, ldu, C, ldc, info):
+        check(lib().tla_strsyl_batched(self.h, batch, n_max, _ptr(n), _ptr(L), _ptr(ldl), _ptr(U), _ptr(ldu),
+                                       _ptr(C), _ptr(ldc), _ptr(info)), "tla_strsyl_batched")
+
+    def strlyap_batched(self, batch, n_max, n, L, ldl, S, lds, info):
+        check(lib().tla_strlyap_batched(self.h, batch, n_max, _ptr(n), _ptr(L), _ptr(ldl), _ptr(S), _ptr(lds),
+                                        _ptr(info)), "tla_strlyap_batched")
 
     def ragged_batched(self, prec, batch, n_max, desc, info, stat=None):
         check(lib().tla_ragged_batched(self.h, _prec(prec), batch, n_max, _ptr(desc), _ptr(info), _ptr(stat)),
@@ -322,13 +338,13 @@ def num_variants(op):
 
 
 # ---------------------------------------------------------- batch helpers
-def to_device_cm(M, device="cuda", ld=None):
+def to_device_cm(M, device="cuda", ld=None, dtype=np.float64):
     """numpy (batch, n, n) indexed [b, i, j] -> column-major batch tensor (batch, n, ld)."""
     import torch
-    M = np.asarray(M, dtype=np.float64)
+    M = np.asarray(M, dtype=dtype)
     b, n = M.shape[0], M.shape[-1]
     ld = ld or n
-    host = np.zeros((b, n, ld), dtype=np.float64)
+    host = np.zeros((b, n, ld), dtype=dtype)
     host[:, :, :n] = np.swapaxes(M, 1, 2)
     return torch.from_numpy(host).to(device)
 
@@ -369,8 +385,8 @@ class Operands:
         self.n = torch.full((self.batch,), n, dtype=torch.int32, device=device)
         self.ptrs, self.lds = [], []
         for m in mats:
-            assert m.dtype == torch.float64 and m.is_contiguous() and m.shape[0] == self.batch
-            stride = m.shape[1] * m.shape[2] * 8
+            assert m.dtype in (torch.float64, torch.float32) and m.is_contiguous() and m.shape[0] == self.batch
+            stride = m.shape[1] * m.shape[2] * m.element_size()
             base = m.data_ptr()
             p = torch.arange(self.batch, dtype=torch.int64, device=device) * stride + base
             self.ptrs.append(p)
@@ -402,6 +418,26 @@ def trlyap(h: Handle, L, S, prec="f64", ops: Operands | None = None):
     ops = ops or Operands(S.shape[1], L, S)
     h.trlyap_batched(prec, ops.batch, ops.n_max, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1],
                      ops.info, ops.stat)
+    return ops
+
+
+def spotrf(h: Handle, A, ops: Operands | None = None):
+    """FP32 I/O and arithmetic, in place on the float32 column-major batch A (batch, n, ld)."""
+    ops = ops or Operands(A.shape[1], A)
+    h.spotrf_batched(ops.batch, ops.n_max, ops.n, ops.ptrs[0], ops.lds[0], ops.info)
+    return ops
+
+
+def strsyl(h: Handle, L, U, C, ops: Operands | None = None):
+    ops = ops or Operands(C.shape[1], L, U, C)
+    h.strsyl_batched(ops.batch, ops.n_max, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1],
+                     ops.ptrs[2], ops.lds[2], ops.info)
+    return ops
+
+
+def strlyap(h: Handle, L, S, ops: Operands | None = None):
+    ops = ops or Operands(S.shape[1], L, S)
+    h.strlyap_batched(ops.batch, ops.n_max, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1], ops.info)
     return ops
 
 

@@ -19,9 +19,9 @@ namespace tla {
 // read above the diagonal returns the mirrored element, and mirrors() tells
 // the tile solvers to store every solved tile below the diagonal also
 // transposed above it.
-template <class T, bool SYM = false>
+template <class T, bool SYM = false, class S = double>
 struct IOView {
-  double* p;
+  S* p;  // storage type of the caller's matrix (FP64, or FP32 for the FP32-I/O entry points)
   int ld, n;
   bool upper_only;
   int r0, c0;
@@ -38,14 +38,14 @@ struct IOView {
     }
     const bool in = r < n && c < n;
     const int rr = r < n ? r : n - 1, cc = c < n ? c : n - 1;
-    const double raw = to_gbl(p)[rr + (size_t)cc * ld];
+    const S raw = to_gbl(p)[rr + (size_t)cc * ld];
     if (!in) return (upper_only && r == c) ? T(1) : T(0);
     return (upper_only && r > c) ? T(0) : T(raw);
   }
   TLA_DI void store(int i, int j, T v) const {
     int r, c;
     coords(i, j, r, c);
-    if (r < n && c < n && !(upper_only && r > c)) to_gbl(p)[r + (size_t)c * ld] = double(v);
+    if (r < n && c < n && !(upper_only && r > c)) to_gbl(p)[r + (size_t)c * ld] = S(v);
   }
   TLA_DI void fence() const { __threadfence_block(); }
   static constexpr bool mirrors() { return SYM; }
@@ -57,30 +57,40 @@ struct IOView {
   TLA_DI IOView t() const { IOView v = *this; v.tr = !tr; return v; }
 };
 
-template <class T>
-TLA_DI IOView<T> ioview(double* p, int ld, int n, bool upper_only) { return IOView<T>{p, ld, n, upper_only, 0, 0, false}; }
+template <class T, class S>
+TLA_DI IOView<T, false, S> ioview(S* p, int ld, int n, bool upper_only) {
+  return IOView<T, false, S>{p, ld, n, upper_only, 0, 0, false};
+}
 
 constexpr int kLargeTB = 16, kLargeNW = 16;
 
 
-template <int NW>
-TLA_DI void large_ctx_init(unsigned char* smem, Ctx<double>& cx, int n, int*& s_info, int init) {
-  double* wb = reinterpret_cast<double*>(smem);
+// T is the element type of both the arithmetic and the caller's matrices:
+// double for the FP64 entry points, float for the FP32-I/O ones (the
+// instance's pointers are then float arrays; KArgs carries them untyped).
+template <int NW, class T = double>
+TLA_DI void large_ctx_init(unsigned char* smem, Ctx<T>& cx, int n, int*& s_info, int init) {
+  T* wb = reinterpret_cast<T*>(smem);
   s_info = reinterpret_cast<int*>(wb + NW * wave_scratch(kLargeTB));
   if (threadIdx.x == 0) *s_info = init;
   __syncthreads();
-  cx = Ctx<double>{n, (n + kLargeTB - 1) / kLargeTB, to_lds(wb + wave_id() * wave_scratch(kLargeTB)), to_lds(s_info)};
+  cx = Ctx<T>{n, (n + kLargeTB - 1) / kLargeTB, to_lds(wb + wave_id() * wave_scratch(kLargeTB)), to_lds(s_info)};
 }
 
-template <int NW, int VAR>
+template <class T>
+TLA_DI T* as_elem(double* p) { return reinterpret_cast<T*>(p); }
+template <class T>
+TLA_DI const T* as_elem(const double* p) { return reinterpret_cast<const T*>(p); }
+
+template <int NW, int VAR, class T = double>
 TLA_DI void potrf_inplace_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
   if (skip_unflagged(g, in)) return;
   if (!validate(in, g.n_max, n)) return;
-  Ctx<double> cx;
+  Ctx<T> cx;
   int* s_info;
-  large_ctx_init<NW>(smem, cx, n, s_info, 0);
-  potrf_blocked<double, kLargeTB, ENG_MFMA, NW, VAR>(ioview<double>(in.c, in.ldc, n, true), cx);
+  large_ctx_init<NW, T>(smem, cx, n, s_info, 0);
+  potrf_blocked<T, kLargeTB, ENG_MFMA, NW, VAR>(ioview<T>(as_elem<T>(in.c), in.ldc, n, true), cx);
   __syncthreads();
   if (threadIdx.x == 0) {
     *in.info = *s_info;
@@ -88,18 +98,18 @@ TLA_DI void potrf_inplace_body(const KArgs& g, const Inst& in, unsigned char* sm
   }
 }
 
-template <int NW, int VAR>
+template <int NW, int VAR, class T = double>
 TLA_DI void trsyl_inplace_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
   if (skip_unflagged(g, in)) return;
   if (!validate(in, g.n_max, n)) return;
-  Ctx<double> cx;
+  Ctx<T> cx;
   int* s_info;
-  large_ctx_init<NW>(smem, cx, n, s_info, INT_MAX);
-  const GView<double> L = gview<double>(in.a, in.lda, n, -1);
-  const GView<double> U = gview<double>(in.b, in.ldb, n, +1);
+  large_ctx_init<NW, T>(smem, cx, n, s_info, INT_MAX);
+  const auto L = gview<T>(as_elem<T>(in.a), in.lda, n, -1);
+  const auto U = gview<T>(as_elem<T>(in.b), in.ldb, n, +1);
   scan_zero_denoms(L, U, n, false, s_info);
-  trsyl_blocked<double, kLargeTB, ENG_MFMA, NW, VAR>(ioview<double>(in.c, in.ldc, n, false), L, U, cx);
+  trsyl_blocked<T, kLargeTB, ENG_MFMA, NW, VAR>(ioview<T>(as_elem<T>(in.c), in.ldc, n, false), L, U, cx);
   __syncthreads();
   if (threadIdx.x == 0) {
     *in.info = *s_info == INT_MAX ? 0 : *s_info;
@@ -107,20 +117,20 @@ TLA_DI void trsyl_inplace_body(const KArgs& g, const Inst& in, unsigned char* sm
   }
 }
 
-template <int NW, int VAR>
+template <int NW, int VAR, class T = double>
 TLA_DI void trlyap_inplace_body(const KArgs& g, const Inst& in, unsigned char* smem) {
   int n;
   if (skip_unflagged(g, in)) return;
   if (!validate(in, g.n_max, n)) return;
-  Ctx<double> cx;
+  Ctx<T> cx;
   int* s_info;
-  large_ctx_init<NW>(smem, cx, n, s_info, INT_MAX);
-  const GView<double> L = gview<double>(in.a, in.lda, n, -1);
+  large_ctx_init<NW, T>(smem, cx, n, s_info, INT_MAX);
+  const auto L = gview<T>(as_elem<T>(in.a), in.lda, n, -1);
   scan_zero_denoms(L, L, n, true, s_info);
   // S is given by its lower triangle: the view reads the diagonal tiles'
   // upper halves from it, and the solved tiles are stored on both sides
-  const IOView<double, true> X{in.c, in.ldc, n, false, 0, 0, false};
-  trlyap_blocked<double, kLargeTB, ENG_MFMA, NW, VAR>(X, L, cx);
+  const IOView<T, true, T> X{as_elem<T>(in.c), in.ldc, n, false, 0, 0, false};
+  trlyap_blocked<T, kLargeTB, ENG_MFMA, NW, VAR>(X, L, cx);
   __syncthreads();
   if (threadIdx.x == 0) {
     *in.info = *s_info == INT_MAX ? 0 : *s_info;

@@ -18,9 +18,9 @@ namespace tla {
 // the referenced triangle (tri -1: lower, +1: upper) read as zero, so padded
 // tiles need no special casing; tri +2 / -2 read a symmetric matrix from its
 // upper / lower triangle.
-template <class T>
+template <class T, class S = double>
 struct GView {
-  const double* p;
+  const S* p;  // storage type of the caller's matrix (FP64, or FP32 for the FP32-I/O entry points)
   int ld, n, tri;
   int r0, c0;
   bool tr;
@@ -34,7 +34,7 @@ struct GView {
       if (swap) { const int t = rr; rr = cc; cc = t; }
     }
     // unconditional load from a clamped address, then select
-    const double raw = to_gbl(p)[rr + (size_t)cc * ld];
+    const S raw = to_gbl(p)[rr + (size_t)cc * ld];
     const bool ok = in && (tri == 0 || tri == 2 || tri == -2 || (tri < 0 ? r >= c : r <= c));
     return ok ? T(raw) : T(0);
   }
@@ -45,8 +45,8 @@ struct GView {
   }
   TLA_DI GView t() const { GView v = *this; v.tr = !tr; return v; }
 };
-template <class T>
-TLA_DI GView<T> gview(const double* p, int ld, int n, int tri) { return GView<T>{p, ld, n, tri, 0, 0, false}; }
+template <class T, class S>
+TLA_DI GView<T, S> gview(const S* p, int ld, int n, int tri) { return GView<T, S>{p, ld, n, tri, 0, 0, false}; }
 
 // ------------------------------------------------------ ingest / egress
 // Copies the n x n global matrix into the np x np work matrix (ld = ldw; in

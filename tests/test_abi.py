@@ -19,6 +19,7 @@ def header_functions():
 def test_header_declares_core_entry_points():
     names = header_functions()
     for n in ["tla_potrf_batched", "tla_trsyl_batched", "tla_trlyap_batched", "tla_ragged_batched",
+              "tla_spotrf_batched", "tla_strsyl_batched", "tla_strlyap_batched",
               "tla_create", "tla_destroy", "tla_tune"]:
         assert n in names
 
