@@ -170,6 +170,23 @@ tla_status tla_strlyap_batched(tla_handle h, int batch, int n_max, const int *n,
 tla_status tla_ragged_batched(tla_handle h, tla_prec prec, int batch, int n_max,
                               const tla_desc *d, int *info, tla_stat *stat);
 
+/* Allocation-free variant of tla_ragged_batched, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, work and results as
+ * tla_ragged_batched with prec = TLA_F64 (the same class workers and
+ * per-instance bodies), but the work-list buffers (cost ranks, key histogram,
+ * class counters, queue) live in a fixed 4 MiB device array that each GPU
+ * holds until the process ends, set up by tla_create; the call allocates
+ * nothing, captures no graph and enqueues its kernels directly on the
+ * handle's stream.  Limits: batch <= 1048576 (larger batches return
+ * TLA_E_ARG before any work is enqueued), n_max <= 128, prec = TLA_F64 only
+ * (the mixed precisions need the handle's workspace: TLA_E_UNSUPPORTED);
+ * stat may be NULL.  Every call on one GPU shares that GPU's array, so calls
+ * that overlap in time on one GPU (several streams or host threads) race;
+ * calls ordered on one stream do not. */
+tla_status tla_ragged_batched_noalloc(tla_handle h, tla_prec prec, int batch, int n_max,
+                                      const tla_desc *d, int *info, tla_stat *stat);
+
 /* ------------------------------------------------------- plans and tuning */
 /* A plan names the kernel that solves one (op, n bucket, precision):
  * variant = blocked-algorithm variant (op specific, see tla_variant_name),

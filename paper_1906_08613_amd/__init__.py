@@ -31,7 +31,7 @@ OPS = {"potrf": POTRF, "trsyl": TRSYL, "trlyap": TRLYAP}
 # every exported symbol of include/tla.h
 SYMBOLS = [
     "tla_create", "tla_destroy", "tla_set_stream", "tla_sync",
-    "tla_potrf_batched", "tla_trsyl_batched", "tla_trlyap_batched", "tla_ragged_batched",
+    "tla_potrf_batched", "tla_trsyl_batched", "tla_trlyap_batched", "tla_ragged_batched", "tla_ragged_batched_noalloc",
     "tla_potrs_batched", "tla_potri_batched",
     "tla_spotrf_batched", "tla_strsyl_batched", "tla_strlyap_batched", "tla_set_plan", "tla_get_plan", "tla_num_candidates", "tla_candidate", "tla_variant_name",
     "tla_tune", "tla_time_plan", "tla_save_table", "tla_load_table", "tla_set_picker",
@@ -91,6 +91,7 @@ def lib():
             "tla_trsyl_batched": (I, [V, I, I, I, P, P, P, P, P, P, P, P, P]),
             "tla_trlyap_batched": (I, [V, I, I, I, P, P, P, P, P, P, P]),
             "tla_ragged_batched": (I, [V, I, I, I, P, P, P]),
+            "tla_ragged_batched_noalloc": (I, [V, I, I, I, P, P, P]),
             "tla_potrs_batched": (I, [V, I, I, P, I, P, P, P, P, P, P]),
             "tla_potri_batched": (I, [V, I, I, P, P, P, P, P, P]),
             "tla_spotrf_batched": (I, [V, I, I, P, P, P, P]),
@@ -211,6 +212,10 @@ class Handle:
     def ragged_batched(self, prec, batch, n_max, desc, info, stat=None):
         check(lib().tla_ragged_batched(self.h, _prec(prec), batch, n_max, _ptr(desc), _ptr(info), _ptr(stat)),
               "tla_ragged_batched")
+
+    def ragged_batched_noalloc(self, prec, batch, n_max, desc, info, stat=None):
+        check(lib().tla_ragged_batched_noalloc(self.h, _prec(prec), batch, n_max, _ptr(desc), _ptr(info),
+                                               _ptr(stat)), "tla_ragged_batched_noalloc")
 
     # ------------------------------------------------------------- plans
     def set_plan(self, op, prec, plan=None):
@@ -525,4 +530,10 @@ class RaggedBatch:
 
 def ragged(h: Handle, rb: RaggedBatch, prec="f64", n_max=None):
     h.ragged_batched(prec, rb.batch, rb.n_max if n_max is None else n_max, rb.desc, rb.info, rb.stat)
+    return rb
+
+
+def ragged_noalloc(h: Handle, rb: RaggedBatch, prec="f64", n_max=None):
+    """The allocation-free ragged entry point (FP64, batch <= 1048576)."""
+    h.ragged_batched_noalloc(prec, rb.batch, rb.n_max if n_max is None else n_max, rb.desc, rb.info, rb.stat)
     return rb

@@ -136,6 +136,9 @@ extern "C" tla_status tla_create(tla_handle* h, int device) {
   hipDeviceProp_t prop;
   TLA_HIP(hipGetDeviceProperties(&prop, device));
   g_lds_limit = (int)prop.sharedMemPerBlock;
+  // the allocation-free entry point's scratch array on this device
+  const tla_status ns = noalloc_init(device);
+  if (ns != TLA_OK) return ns;
   tla_ctx* c = new (std::nothrow) tla_ctx();
   if (!c) return TLA_E_NOMEM;
   c->device = device;

@@ -56,6 +56,8 @@ bool table_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* p);
 bool mlp_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* p);
 void mlp_release(tla_ctx* h);
 void ragged_release(tla_ctx* h);
+// Per-device set-up of the allocation-free ragged path (tla_ragged.hip).
+tla_status noalloc_init(int device);
 tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& a);
 size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int placement);
 int choose_placement(tla_ctx* h, int op, int prec, const tla_plan& p, int ntmax, size_t* lds);

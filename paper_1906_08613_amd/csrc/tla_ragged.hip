@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -474,4 +475,68 @@ extern "C" tla_status tla_ragged_batched(tla_handle h, tla_prec prec, int batch,
   if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) { hipGraphDestroy(graph); return TLA_E_HIP; }
   s->graphs.push_back({d, batch, n_max, prec, info, st, (void*)h->stream, exec, graph});
   return hipGraphLaunch(exec, h->stream) == hipSuccess ? TLA_OK : TLA_E_HIP;
+}
+
+// ----------------------------------------------------- allocation-free path
+// For callers that cannot allocate (code under HIP graph capture, serving
+// loops): the work-list buffers live in one file-scope device array instead of
+// handle-owned allocations.  Layout in ints: the cost-rank table, the key
+// histogram and offsets, the class ranges and counters, then the queue of up
+// to kNoAllocMaxBatch instances (4 MiB in all).
+namespace tla {
+constexpr int kNoAllocMaxBatch = 1 << 20;
+constexpr int kNaRank = 0, kNaKeyCount = 512, kNaKeyOff = kNaKeyCount + 1280, kNaCls = kNaKeyOff + 1280,
+              kNaQueue = 4096;
+static_assert(3 * (kMaxN + 1) <= kNaKeyCount - kNaRank && kRagKeys <= 1280 && kNaCls + 16 <= kNaQueue,
+              "scratch layout");
+constexpr int kNaInts = kNaQueue + kNoAllocMaxBatch;
+constexpr int kNaMaxDevices = 64;
+}  // namespace tla
+
+// Each GPU holds its own copy; host code reaches it only through the address
+// hipGetSymbolAddress returns for that device (never through this name).
+static __device__ __align__(256) int scratch[tla::kNaInts];
+
+namespace tla {
+static int* g_na_ptr[kNaMaxDevices] = {};
+
+// Called once per device by tla_create with that device current: looks up
+// this device's copy of the scratch array and writes the cost-rank table
+// into it (the table never changes afterwards).
+tla_status noalloc_init(int device) {
+  if (device < 0 || device >= kNaMaxDevices) return TLA_E_UNSUPPORTED;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  if (g_na_ptr[device]) return TLA_OK;
+  int* ptr = nullptr;
+  if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TLA_E_HIP;
+  const std::vector<int> rank = cost_rank();
+  if (hipMemcpy(ptr + kNaRank, rank.data(), rank.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return TLA_E_HIP;
+  g_na_ptr[device] = ptr;
+  return TLA_OK;
+}
+}  // namespace tla
+
+// Same work and results as tla_ragged_batched for FP64 (the same class
+// workers and per-instance bodies), enqueued directly on the handle's stream:
+// no allocation, no graph capture.  Every call on a GPU shares that GPU's
+// scratch array, so calls that overlap on one GPU race.
+extern "C" tla_status tla_ragged_batched_noalloc(tla_handle h, tla_prec prec, int batch, int n_max,
+                                                 const tla_desc* d, int* info, tla_stat* stat) {
+  if (!h || batch < 0 || n_max < 0 || prec < TLA_F64 || prec > TLA_MIXED_BF16) return TLA_E_ARG;
+  if (batch > kNoAllocMaxBatch) return TLA_E_ARG;
+  if (batch == 0) return TLA_OK;
+  if (!d || !info) return TLA_E_ARG;
+  if (n_max > kMaxN) return TLA_E_UNSUPPORTED;
+  if (prec != TLA_F64) return TLA_E_UNSUPPORTED;
+  if (h->device < 0 || h->device >= kNaMaxDevices || !g_na_ptr[h->device]) return TLA_E_HIP;
+  if (hipSetDevice(h->device) != hipSuccess) return TLA_E_HIP;
+  RagLaunch plan[kRagMaxLaunches];
+  int nplan = 0;
+  tla_status ps = rag_plan(h, prec, batch, n_max, stat, plan, &nplan);
+  if (ps != TLA_OK) return ps;
+  int* p = g_na_ptr[h->device];
+  const RagArgs r{d, batch, n_max, info, stat, p + kNaRank, p + kNaKeyCount, p + kNaKeyOff, p + kNaQueue, p + kNaCls};
+  return rag_enqueue(h->stream, r, plan, nplan);
 }
