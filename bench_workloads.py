@@ -53,43 +53,49 @@ def potrf16(a):
     n, batch, reps = 16, 1024, 200
     h = tla.Handle(0)
     A = I.potrf_problem("cfg0", n, batch)
-    dA = tla.to_device_cm(np.triu(A))
-    pristine = dA.clone()
-    ops = tla.Operands(n, dA)
-    # graph of `reps` launches on a side stream; restore copies are outside it
+    # one input copy per launch of the graph, so that every launch factors the
+    # pristine matrices (an in-place launch would otherwise re-factor the
+    # previous launch's output); all copies are restored outside the timed region
+    pristine = tla.to_device_cm(np.triu(A))
+    copies = pristine.unsqueeze(0).repeat(reps, 1, 1, 1).contiguous()
+    ops = [tla.Operands(n, copies[r]) for r in range(reps)]
     s = torch.cuda.Stream()
     h.set_stream(s)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.stream(s):
-        h.potrf_batched("f64", batch, n, ops.n, ops.ptrs[0], ops.lds[0], ops.info, ops.stat)  # warm-up
+        o = ops[0]
+        h.potrf_batched("f64", batch, n, o.n, o.ptrs[0], o.lds[0], o.info, o.stat)  # warm-up
         torch.cuda.synchronize()
         with torch.cuda.graph(g, stream=s):
-            for _ in range(reps):
-                h.potrf_batched("f64", batch, n, ops.n, ops.ptrs[0], ops.lds[0], ops.info, ops.stat)
+            for o in ops:
+                h.potrf_batched("f64", batch, n, o.n, o.ptrs[0], o.lds[0], o.info, o.stat)
     times = []
     for _ in range(5):
-        dA.copy_(pristine)
+        copies.copy_(pristine.unsqueeze(0).expand_as(copies))
         torch.cuda.synchronize()
         e0, e1 = _events(torch)
-        e0.record(s)
-        g.replay()
-        e1.record(s)
+        # the graph replays on the current stream: the events bracket it there
+        with torch.cuda.stream(s):
+            e0.record()
+            g.replay()
+            e1.record()
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1) * 1e-3 / reps)
-    # one clean solve for the check
-    dA.copy_(pristine)
-    h.potrf_batched("f64", batch, n, ops.n, ops.ptrs[0], ops.lds[0], ops.info, ops.stat)
-    torch.cuda.synchronize()
-    X = np.triu(tla.from_device_cm(dA))
+    # the last replay's outputs: every copy holds one launch's factor
+    X0 = np.triu(tla.from_device_cm(copies[0]))
+    Xl = np.triu(tla.from_device_cm(copies[reps - 1]))
     Xr, _ = oracle.potrf_batch(A[:64])
     t = float(np.median(times))
     t0 = time.perf_counter()
     oracle.potrf_batch(A)
     tc = time.perf_counter() - t0
-    print(json.dumps({"workload": "potrf f64 n=16 x1024 (graph of 200 launches)", "solves_per_s": batch / t,
+    print(json.dumps({"workload": "potrf f64 n=16 x1024 (graph of 200 launches, each on its own pristine copy)",
+                      "solves_per_s": batch / t,
                       "gflops": batch * _flops(0, n) / t / 1e9, "gbs": batch * _bytes(0, n) / t / 1e9,
                       "us_per_launch": t * 1e6,
-                      "fwd_err_max": float(oracle.forward_error(X[:64], Xr).max()),
+                      "fwd_err_max": float(max(oracle.forward_error(X0[:64], Xr).max(),
+                                               oracle.forward_error(Xl[:64], Xr).max())),
+                      "info_nonzero": int(sum(int((o.info != 0).sum()) for o in (ops[0], ops[-1]))),
                       "cpu_oracle_solves_per_s": batch / tc, "cpu_threads": oracle.max_threads()}))
 
 

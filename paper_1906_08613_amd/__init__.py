@@ -335,11 +335,18 @@ def variant_name(op, v):
 
 
 def num_variants(op):
-    """Number of blocked-algorithm variants of op (names are valid for 0..count-1)."""
+    """Number of variants of op (names are valid for 0..count-1): the blocked
+    algorithms, then (Sylvester, Lyapunov) the splitting-iteration solve of the
+    mixed precisions."""
     v = 0
     while variant_name(op, v) != "invalid":
         v += 1
     return v
+
+
+def blocked_variants(op):
+    """Indices of the blocked-algorithm variants of op (every precision and size)."""
+    return [v for v in range(num_variants(op)) if variant_name(op, v) != "jacobi-sweeps"]
 
 
 # ---------------------------------------------------------- batch helpers

@@ -19,14 +19,22 @@ using namespace tla;
 // ------------------------------------------------------------------ plans
 namespace tla {
 
-static const char* kVarNames[3][8] = {
-    {"right-looking", "left-looking", "bordered", nullptr, nullptr, nullptr, nullptr, nullptr},
+static const char* kVarNames[3][9] = {
+    {"right-looking", "left-looking", "bordered", nullptr, nullptr, nullptr, nullptr, nullptr, nullptr},
     {"tile-wavefront", "rows-lazy", "rows-eager", "cols-lazy", "cols-eager", "2d-bordered", "2d-border-lazy",
-     "2d-border-eager"},
-    {"tile-wavefront", "rows-lazy", "right-looking", "cols-lazy", nullptr, nullptr, nullptr, nullptr}};
-static const int kNumVar[3] = {3, 8, 4};  // CHOL_NVAR, SYL_NVAR, LYA_NVAR (checked where the kernels are listed)
+     "2d-border-eager", "jacobi-sweeps"},
+    {"tile-wavefront", "rows-lazy", "right-looking", "cols-lazy", "jacobi-sweeps", nullptr, nullptr, nullptr, nullptr}};
+// blocked-algorithm variants (CHOL_NVAR, SYL_NVAR, LYA_NVAR, checked where the
+// kernels are listed), then the splitting-iteration solve of the mixed
+// precisions for the Sylvester and Lyapunov equations
+static const int kNumBlocked[3] = {3, 8, 4};
+static const int kNumVar[3] = {3, 9, 5};
 
 int num_variants(int op) { return (op >= 0 && op < 3) ? kNumVar[op] : 0; }
+
+bool is_jacobi(int op, int variant) {
+  return (op == TLA_TRSYL || op == TLA_TRLYAP) && variant == kNumBlocked[op];
+}
 
 bool plan_valid(int op, const tla_plan& p) {
   if (op < 0 || op > 2) return false;
@@ -41,16 +49,31 @@ bool plan_valid(int op, const tla_plan& p) {
   if (p.place < 0 || p.place > 3) return false;
   if (op == TLA_POTRF && p.place == 1) return false;
   if (p.place == 3 && !(p.tile == 16 && p.engine == 1)) return false;
+  // the splitting-iteration solve: 16 x 16 matrix-core tiles, registers, one
+  // wave per tile column (waves is not a choice there)
+  if (is_jacobi(op, p.variant) && !(p.tile == 16 && p.engine == 1 && p.waves == 1 && p.place == 3)) return false;
   return true;
 }
 
 // candidates: variant x (tile, engine) x waves x coefficient placement 0..2,
 // then variant x waves with placement 3 (16 x 16 matrix-core tiles only)
 static int num_places(int op) { return op == TLA_POTRF ? 2 : 3; }
-static int num_candidates_lds(int op) { return num_variants(op) * kNumTE * kNumNW * num_places(op); }
-int num_candidates(int op) { return num_candidates_lds(op) + num_variants(op) * kNumNW; }
+static int num_candidates_lds(int op) { return kNumBlocked[op] * kNumTE * kNumNW * num_places(op); }
+static int num_candidates_blocked(int op) { return num_candidates_lds(op) + kNumBlocked[op] * kNumNW; }
+int num_candidates(int op) {
+  if (op < 0 || op > 2) return 0;
+  return num_candidates_blocked(op) + (kNumVar[op] - kNumBlocked[op]);
+}
 bool candidate(int op, int i, tla_plan* p) {
   if (i < 0 || i >= num_candidates(op)) return false;
+  if (i >= num_candidates_blocked(op)) {  // the splitting-iteration solve (mixed precisions only)
+    p->variant = kNumBlocked[op];
+    p->tile = 16;
+    p->engine = 1;
+    p->waves = 1;
+    p->place = 3;
+    return true;
+  }
   if (i >= num_candidates_lds(op)) {
     i -= num_candidates_lds(op);
     const int nwi = i % kNumNW;
@@ -82,6 +105,18 @@ bool candidate(int op, int i, tla_plan* p) {
 // workspace.
 tla_plan default_plan(int op, int n, int prec) {
   tla_plan p;
+  // Sylvester and Lyapunov, mixed: the splitting-iteration solve where it
+  // measured faster than the blocked mixed kernels (BF16 products up to
+  // n = 64, FP32 products up to n = 32)
+  if ((op == TLA_TRSYL || op == TLA_TRLYAP) &&
+      ((prec == TLA_MIXED_BF16 && n <= kJacobiMaxN) || (prec == TLA_MIXED_F32 && n <= 32))) {
+    p.variant = op == TLA_TRSYL ? 8 : 4;
+    p.tile = 16;
+    p.engine = 1;
+    p.waves = 1;
+    p.place = 3;
+    return p;
+  }
   p.variant = (op == TLA_POTRF && n > kMaxN) ? 1 : 0;
   p.tile = 16;
   p.engine = 1;
@@ -294,11 +329,40 @@ static tla_status ensure_work(tla_ctx* h, KArgs& a, int pl) {
   return TLA_OK;
 }
 
+// The splitting-iteration mixed solve, then the FP64 pass over the instances
+// it left unconverged (the in-place FP64 tile-wavefront kernel, one wave).
+static tla_status launch_jacobi(tla_ctx* h, int op, int prec, KArgs a) {
+  size_t lds = 0;
+  int waves = 1;
+  KFn fn = jacobi_kernel(op, prec, a.n_max, &lds, &waves);
+  if (!fn || lds > (size_t)h->lds_limit) return TLA_E_UNSUPPORTED;
+  if (!a.stat) {
+    // the FP64 pass reads the refinement records
+    tla_status s = ensure_buffers(h, 0, a.batch);
+    if (s != TLA_OK) return s;
+    a.stat = h->stat_buf;
+  }
+  a.ntmax = (a.n_max + 15) / 16;
+  if (getenv("TLA_LOG"))
+    fprintf(stderr, "tla: op %d prec %d batch %d n_max %d jacobi-sweeps waves %d lds %zu\n", op, prec, a.batch,
+            a.n_max, waves, lds);
+  tla_status s = launch_one(h, fn, lds, a.batch, waves, a);
+  if (s != TLA_OK) return s;
+  KFn fb = inplace_kernel(op, 0, 0);
+  if (!fb) return TLA_E_UNSUPPORTED;
+  a.only_flagged = 1;
+  return launch_one(h, fb, inplace_lds_bytes(1), a.batch, 1, a);
+}
+
 tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& a0) {
   KArgs a = a0;
   a.tau = h->tau;
   a.max_iter = h->max_iter;
   a.only_flagged = 0;
+  if (is_jacobi(op, p.variant)) {
+    if (prec == TLA_F64 || a.n_max > kJacobiMaxN) return TLA_E_UNSUPPORTED;
+    return launch_jacobi(h, op, prec, a);
+  }
   if (a.n_max > kMaxN) {
     // large sizes: FP64 in place over global memory, variant from the plan.
     // (The mixed precisions are not offered here: their 16-wave kernels with
@@ -340,12 +404,21 @@ tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& 
   return launch_one(h, fb, lds64, a.batch, p.waves, a);
 }
 
+// Whether a plan exists for (op, prec, n): the splitting-iteration solve has
+// BF16 and FP32 products and n <= kJacobiMaxN only (the blocked plans run
+// everywhere; placements that do not fit move to a larger one at launch).
+bool plan_runs(int op, int prec, int n, const tla_plan& p) {
+  if (is_jacobi(op, p.variant)) return (prec == TLA_MIXED_F32 || prec == TLA_MIXED_BF16) && n <= kJacobiMaxN;
+  return true;
+}
+
 tla_plan pick_plan(tla_ctx* h, int op, int n, int prec, int batch) {
   auto f = h->forced.find(op * 8 + prec);
   if (f != h->forced.end()) return f->second;
   tla_plan p;
   if (h->picker == TLA_PICK_MLP && mlp_pick(h, op, n, prec, batch, &p)) return p;
-  if (h->picker != TLA_PICK_DEFAULT && table_pick(h, op, n, prec, batch, &p)) return p;
+  // a table entry of a nearby size may name a plan that does not exist at n
+  if (h->picker != TLA_PICK_DEFAULT && table_pick(h, op, n, prec, batch, &p) && plan_runs(op, prec, n, p)) return p;
   return default_plan(op, n, prec);
 }
 

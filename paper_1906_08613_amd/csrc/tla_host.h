@@ -62,6 +62,8 @@ tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& 
 size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int placement);
 int choose_placement(tla_ctx* h, int op, int prec, const tla_plan& p, int ntmax, size_t* lds);
 bool plan_valid(int op, const tla_plan& p);
+bool is_jacobi(int op, int variant);
+bool plan_runs(int op, int prec, int n, const tla_plan& p);
 int num_candidates(int op);
 bool candidate(int op, int i, tla_plan* p);
 tla_plan default_plan(int op, int n, int prec);

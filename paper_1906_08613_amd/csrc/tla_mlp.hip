@@ -21,7 +21,7 @@
 
 namespace tla {
 
-constexpr int kMlpIn = 28, kMlpH = 64;
+constexpr int kMlpIn = 29, kMlpH = 64;
 constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kMlpH * kMlpIn, kOffW2 = kOffB1 + kMlpH, kOffB2 = kOffW2 + kMlpH * kMlpH,
               kOffW3 = kOffB2 + kMlpH, kOffB3 = kOffW3 + kMlpH, kMlpParams = kOffB3 + 1;
 
@@ -40,9 +40,9 @@ struct MlpState {
 
 // ----------------------------------------------------------------- features
 // op one-hot (3), precision one-hot (4), n terms (4), batch (1), variant
-// one-hot (8), tile 16 (1), matrix cores (1), waves one-hot (3), tile count
-// squared (1), coefficients through the caches (1), solved in place in global
-// memory (1).
+// one-hot (9: the blocked variants, then the splitting-iteration solve), tile
+// 16 (1), matrix cores (1), waves one-hot (3), tile count squared (1),
+// coefficients through the caches (1), solved in place in global memory (1).
 void mlp_features(int op, int n, int prec, int batch, const tla_plan& p, float* f) {
   for (int i = 0; i < kMlpIn; ++i) f[i] = 0.f;
   f[op] = 1.f;
@@ -53,13 +53,13 @@ void mlp_features(int op, int n, int prec, int batch, const tla_plan& p, float* 
   f[9] = (nn / 128.f) * (nn / 128.f);
   f[10] = (float)((n + p.tile - 1) / p.tile) / 16.f;
   f[11] = std::log2((float)std::max(batch, 1)) / 16.f;
-  f[12 + std::min(p.variant, 7)] = 1.f;
-  f[20] = p.tile == 16 ? 1.f : 0.f;
-  f[21] = p.engine ? 1.f : 0.f;
-  f[22 + (p.waves == 1 ? 0 : (p.waves == 2 ? 1 : 2))] = 1.f;
-  f[25] = f[10] * f[10];
-  f[26] = (p.place == 1 || p.place == 2) ? 1.f : 0.f;
-  f[27] = p.place == 3 ? 1.f : 0.f;
+  f[12 + std::min(p.variant, 8)] = 1.f;
+  f[21] = p.tile == 16 ? 1.f : 0.f;
+  f[22] = p.engine ? 1.f : 0.f;
+  f[23 + (p.waves == 1 ? 0 : (p.waves == 2 ? 1 : 2))] = 1.f;
+  f[26] = f[10] * f[10];
+  f[27] = (p.place == 1 || p.place == 2) ? 1.f : 0.f;
+  f[28] = p.place == 3 ? 1.f : 0.f;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -229,6 +229,7 @@ bool mlp_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* best) {
     tla_plan p;
     candidate(op, c, &p);
     size_t lds;
+    if (!plan_runs(op, prec, n, p)) continue;
     if (choose_placement(h, op, prec, p, (n + p.tile - 1) / p.tile, &lds) < 0) continue;
     plans[usable] = p;
     mlp_features(op, n, prec, batch, p, &X[(size_t)usable * kMlpIn]);

@@ -50,3 +50,13 @@ size_t potrs_lds_bytes(int nw);
 // Identity into c (n x n, ldc) of every valid instance; 256 threads.
 KFn potri_eye_kernel();
 }  // namespace tla
+
+namespace tla {
+// Mixed precision with the splitting-iteration low-precision solve
+// (tla_jacobi.hip): Sylvester and Lyapunov, n <= kJacobiMaxN, products on the
+// BF16 (split into head and tail) or FP32 matrix cores.  Returns null when not
+// built for (op, prec, n_max); *lds / *waves receive the launch shape.
+constexpr int kJacobiMaxN = 64;
+KFn jacobi_kernel(int op, int prec, int n_max, size_t* lds, int* waves);
+}  // namespace tla
+

@@ -38,16 +38,20 @@ def test_host_only_queries():
     if not os.path.exists(tla.LIB_PATH):
         pytest.skip("libtla.so not built")
     # variants x 3 tile/engine x 3 waves x LDS placements, plus variants x 3 waves in place (placement 3)
+    # (Sylvester and Lyapunov: plus the one splitting-iteration candidate of the mixed precisions)
     assert tla.num_candidates("potrf") == 54 + 9
-    assert tla.num_candidates("trsyl") == 216 + 24
-    assert tla.num_candidates("trlyap") == 108 + 12
+    assert tla.num_candidates("trsyl") == 216 + 24 + 1
+    assert tla.num_candidates("trlyap") == 108 + 12 + 1
+    p = tla.candidate("trsyl", 240)
+    assert (p.variant, p.tile, p.engine, p.waves, p.place) == (8, 16, 1, 1, 3)
     p = tla.candidate("trsyl", 216 + 4)
     assert (p.variant, p.tile, p.engine, p.waves, p.place) == (1, 16, 1, 2, 3)
     assert tla.variant_name("trsyl", 0) == "tile-wavefront"
     assert [tla.variant_name("trsyl", v) for v in (5, 6, 7)] == ["2d-bordered", "2d-border-lazy", "2d-border-eager"]
     assert tla.variant_name("trlyap", 3) == "cols-lazy"
-    assert tla.variant_name("trsyl", 8) == "invalid"
-    assert [tla.num_variants(op) for op in ("potrf", "trsyl", "trlyap")] == [3, 8, 4]
+    assert tla.variant_name("trsyl", 8) == "jacobi-sweeps" and tla.variant_name("trlyap", 4) == "jacobi-sweeps"
+    assert tla.variant_name("trsyl", 9) == "invalid"
+    assert [tla.num_variants(op) for op in ("potrf", "trsyl", "trlyap")] == [3, 9, 5]
     assert tla.lib().tla_status_string(4).decode() == "unsupported"
     # a null handle is rejected before any device work
     assert tla.lib().tla_potrf_batched(None, 0, 1, 4, None, None, None, None, None) == tla.E_ARG

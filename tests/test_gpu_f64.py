@@ -30,8 +30,10 @@ def h():
 
 def all_plans(op):
     # place 2 (solution in the workspace) exists for the mixed kernels only;
-    # place 3 (in place in global memory) is an FP64 placement and included
-    return [p for p in (tla.candidate(op, i).astuple() for i in range(tla.num_candidates(op))) if p[4] != 2]
+    # place 3 (in place in global memory) is an FP64 placement and included;
+    # the splitting-iteration solve is a mixed-precision plan
+    return [p for p in (tla.candidate(op, i).astuple() for i in range(tla.num_candidates(op)))
+            if p[4] != 2 and tla.variant_name(op, p[0]) != "jacobi-sweeps"]
 
 
 def run_potrf(h, A, plan=None, prec="f64"):

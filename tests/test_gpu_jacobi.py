@@ -1,0 +1,191 @@
+"""GPU parity of the mixed-precision Sylvester and Lyapunov solves whose
+low-precision solve is the splitting (Jacobi) iteration on the matrix cores
+(variant "jacobi-sweeps", n <= 64), against the FP64 oracle.
+
+Gate as for the other mixed kernels: backward error eta <= 1e-12 per
+instance, forward error within max(1e-12, 4 n kappa u64, 2 kappa tau).
+Instances whose iteration does not contract (strict triangles large against
+the diagonal sums) must come out of the FP64 second pass, flagged.
+"""
+import numpy as np
+import pytest
+
+import paper_1906_08613_amd as tla
+from paper_1906_08613_amd import inputs as I
+from tests.gpu_util import rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+U64 = 2.0 ** -53
+TAU = 1e-13
+PRECS = ["mixed_bf16", "mixed_f32"]
+JAC = {"trsyl": (8, 16, 1, 1, 3), "trlyap": (4, 16, 1, 1, 3)}
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hd = tla.Handle(0)
+    yield hd
+    hd.set_plan("trsyl", "mixed_bf16", None)
+    hd.close()
+
+
+def fwd_tol(n, kappa):
+    return max(1e-12, 4 * n * kappa * U64, 2 * kappa * TAU)
+
+
+def run(h, op, mats, prec, ld_pad=0, n_vec=None):
+    h.set_plan(op, prec, JAC[op])
+    try:
+        n = mats[0].shape[-1]
+        if op == "trsyl":
+            dL, dU, dC = (tla.to_device_cm(m, ld=n + ld_pad) for m in mats)
+            ops = tla.Operands(n, dL, dU, dC)
+            if n_vec is not None:
+                ops.n.copy_(torch.tensor(n_vec, dtype=torch.int32))
+            tla.trsyl(h, dL, dU, dC, prec, ops=ops)
+            out = dC
+        else:
+            dL, dS = tla.to_device_cm(mats[0], ld=n + ld_pad), tla.to_device_cm(np.tril(mats[1]), ld=n + ld_pad)
+            ops = tla.Operands(n, dL, dS)
+            if n_vec is not None:
+                ops.n.copy_(torch.tensor(n_vec, dtype=torch.int32))
+            tla.trlyap(h, dL, dS, prec, ops=ops)
+            out = dS
+        torch.cuda.synchronize()
+    finally:
+        h.set_plan(op, prec, None)
+    return tla.from_device_cm(out)[:, :, :n], ops
+
+
+def oracle(orc, op, mats):
+    if op == "trsyl":
+        X, info = orc.trsyl_batch(*mats)
+        return X, info, orc.eta_trsyl_batch
+    X, info = orc.trlyap_batch(*mats)
+    return X, info, orc.eta_trlyap_batch
+
+
+def kappa_problem(op, n, batch, kappa, tag):
+    return I.trsyl_kappa(tag, n, batch, kappa) if op == "trsyl" else I.trlyap_kappa(tag, n, batch, kappa)
+
+
+@pytest.mark.parametrize("op", ["trsyl", "trlyap"])
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("kappa", [1e2, 1e4, 1e6])
+@pytest.mark.parametrize("n", [1, 5, 16, 17, 31, 32, 33, 50, 64])
+def test_jacobi_matches_oracle(h, orc, op, prec, kappa, n):
+    print(f"jacobi {op} {prec} kappa={kappa:g} n={n}", flush=True)
+    mats = kappa_problem(op, n, 12, kappa, "jac")
+    X, ops = run(h, op, mats, prec)
+    Xr, ir, eta_fn = oracle(orc, op, mats)
+    st = tla.stat_view(ops.stat)
+    assert np.all(ops.info.cpu().numpy() == ir)
+    assert eta_fn(*mats, X).max() <= 1e-12, st
+    assert rel_err(X, Xr).max() <= fwd_tol(n, kappa)
+    # these inputs contract fast: every instance converges in the mixed kernel
+    assert np.all(st["flags"] & tla.STAT_CONVERGED), st
+    assert st["iters"].max() <= 3 and np.all(st["eta"] <= TAU)
+    if op == "trlyap":
+        assert np.array_equal(X, np.swapaxes(X, 1, 2))
+
+
+@pytest.mark.parametrize("op", ["trsyl", "trlyap"])
+@pytest.mark.parametrize("prec", PRECS)
+def test_jacobi_plain_inputs_and_padding(h, orc, op, prec):
+    # the sweep workload's operands (diagonals uniform on [1, 2], strict
+    # triangles N(0,1)/n), a padded leading dimension and uneven n per instance
+    n, batch = 60, 10
+    mats = I.trsyl_problem("jacpad", n, batch) if op == "trsyl" else I.trlyap_problem("jacpad", n, batch)
+    n_vec = [60, 1, 17, 33, 48, 59, 0, 16, 32, 45]
+    X, ops = run(h, op, mats, prec, ld_pad=3, n_vec=n_vec)
+    info = ops.info.cpu().numpy()
+    assert np.all(info == 0)
+    for b, m in enumerate(n_vec):
+        if m == 0:
+            continue
+        sub = tuple(M[b:b + 1, :m, :m] for M in mats)
+        Xr, _, eta_fn = oracle(orc, op, sub)
+        Xb = X[b:b + 1, :m, :m]
+        assert eta_fn(*sub, Xb).max() <= 1e-12, (b, m)
+        assert rel_err(Xb, Xr).max() <= 1e-12, (b, m)
+        # nothing outside the leading m x m block was written
+        full = mats[-1][b] if op == "trsyl" else np.tril(mats[1][b])
+        assert np.array_equal(X[b, m:, :], full[m:, :]) and np.array_equal(X[b, :m, m:], full[:m, m:])
+
+
+@pytest.mark.parametrize("op", ["trsyl", "trlyap"])
+@pytest.mark.parametrize("scale", [3.0, 1e3])
+def test_jacobi_large_strict_triangles(h, orc, op, scale):
+    # strict triangles of size `scale` against diagonal sums of 2-4.  At 3 the
+    # sweep still terminates (the strict parts are nilpotent: exact after
+    # 2n - 1 sweeps) or the instance is flagged; at 1000 the intermediate
+    # iterates overflow FP32 and every instance must be flagged and solved by
+    # the FP64 pass, whose result is the FP64 kernel's bit for bit.
+    n, batch = 40, 6
+    rng = np.random.default_rng(5)
+    L = np.tril(rng.standard_normal((batch, n, n)) * scale)
+    L[:, np.arange(n), np.arange(n)] = rng.uniform(1, 2, (batch, n))
+    U = np.triu(rng.standard_normal((batch, n, n)) * scale)
+    U[:, np.arange(n), np.arange(n)] = rng.uniform(1, 2, (batch, n))
+    C = rng.standard_normal((batch, n, n))
+    S = C + np.swapaxes(C, 1, 2)
+    mats = (L, U, C) if op == "trsyl" else (L, S)
+    X, ops = run(h, op, mats, "mixed_bf16")
+    st = tla.stat_view(ops.stat)
+    flagged = (st["flags"] & (tla.STAT_FALLBACK | tla.STAT_BREAKDOWN)) != 0
+    conv = (st["flags"] & tla.STAT_CONVERGED) != 0
+    assert np.all(flagged | conv), st
+    Xr, ir, eta_fn = oracle(orc, op, mats)
+    assert np.all(ops.info.cpu().numpy() == ir)
+    if scale > 100:
+        # (the solution's entries reach 1e190 here: no norm of it is finite)
+        assert np.all(flagged), st
+        h.set_plan(op, "f64", None)
+        if op == "trsyl":
+            dL, dU, dC = (tla.to_device_cm(m) for m in mats)
+            tla.trsyl(h, dL, dU, dC, "f64")
+            Y = dC
+        else:
+            dL, dS = tla.to_device_cm(L), tla.to_device_cm(np.tril(S))
+            tla.trlyap(h, dL, dS, "f64")
+            Y = dS
+        torch.cuda.synchronize()
+        assert np.array_equal(X, tla.from_device_cm(Y))
+    else:
+        assert eta_fn(*mats, X).max() <= 1e-12
+        assert rel_err(X, Xr).max() <= 1e-10
+
+
+@pytest.mark.parametrize("op", ["trsyl", "trlyap"])
+def test_jacobi_zero_denominator_and_nonfinite(h, orc, op):
+    n, batch = 24, 4
+    mats = [m.copy() for m in kappa_problem(op, n, batch, 1e2, "jacz")]
+    # instance 1: l_33 = -u_77 (trsyl) / l_55 = 0 (trlyap): exact zero denominator
+    if op == "trsyl":
+        mats[0][1, 3, 3] = 1.0
+        mats[1][1, 7, 7] = -1.0
+    else:
+        mats[0][1, 5, 5] = 0.0
+    # instance 2: a NaN in the right-hand side
+    mats[-1][2, 4, 2] = np.nan
+    X, ops = run(h, op, mats, "mixed_bf16")
+    Xr, ir, _ = oracle(orc, op, mats)
+    info = ops.info.cpu().numpy()
+    st = tla.stat_view(ops.stat)
+    assert info[1] == ir[1] and info[1] > 0
+    assert st["flags"][2] & tla.STAT_NONFINITE
+    for b in (0, 3):
+        assert info[b] == 0 and st["flags"][b] & tla.STAT_CONVERGED
+        assert rel_err(X[b:b + 1], Xr[b:b + 1]).max() <= 1e-12
+
+
+def test_jacobi_not_offered_for_fp64_fp16_or_large_n(h):
+    L, U, C = I.trsyl_problem("jacu", 80, 2)
+    for prec, mats in (("f64", (L[:, :40, :40], U[:, :40, :40], C[:, :40, :40])), ("mixed_f16", (L[:, :40, :40], U[:, :40, :40], C[:, :40, :40])),
+                       ("mixed_bf16", (L, U, C))):
+        with pytest.raises(tla.TlaError):
+            run(h, "trsyl", tuple(np.ascontiguousarray(m) for m in mats), prec)

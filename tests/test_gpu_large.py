@@ -45,7 +45,7 @@ def test_large_potrf_variants(h, orc, n):
 def test_large_trsyl_variants(h, orc, n):
     L, U, C = I.trsyl_problem("large", n, 2)
     Xr, _ = orc.trsyl_batch(L, U, C)
-    for v in range(tla.num_variants("trsyl")):
+    for v in tla.blocked_variants("trsyl"):
         print(f"trsyl n={n} v={v}", flush=True)
         h.set_plan("trsyl", "f64", (v, 16, 1, 4, 0))
         dL, dU, dC = tla.to_device_cm(L), tla.to_device_cm(U), tla.to_device_cm(C)
@@ -60,7 +60,7 @@ def test_large_trsyl_variants(h, orc, n):
 def test_large_trlyap_variants(h, orc, n):
     L, S = I.trlyap_problem("large", n, 2)
     Xr, _ = orc.trlyap_batch(L, S)
-    for v in range(tla.num_variants("trlyap")):
+    for v in tla.blocked_variants("trlyap"):
         print(f"trlyap n={n} v={v}", flush=True)
         h.set_plan("trlyap", "f64", (v, 16, 1, 4, 0))
         dL, dS = tla.to_device_cm(L), tla.to_device_cm(np.tril(S))

@@ -196,6 +196,12 @@ def test_every_mixed_plan(h, orc, op):
         for i in range(tla.num_candidates(op)):
             plan = tla.candidate(op, i).astuple()
             print(f"{op} {prec} plan={plan}", flush=True)
+            if prec == "mixed_f16" and tla.variant_name(op, plan[0]) == "jacobi-sweeps":
+                # the splitting-iteration solve has BF16 and FP32 products only
+                with pytest.raises(tla.TlaError):
+                    solve(h, op, mats, prec, plan)
+                h.set_plan(op, prec, None)
+                continue
             X, ops = solve(h, op, mats, prec, plan)
             assert eta_fn(*mats, X).max() <= 1e-12, (prec, plan)
             assert rel_err(X, Xr).max() <= fwd_tol(n, 1e3), (prec, plan)
