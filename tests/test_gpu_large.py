@@ -89,3 +89,43 @@ def test_large_sampled_parity_512(h, orc):
     tla.potrf(h, dA)
     torch.cuda.synchronize()
     assert orc.eta_potrf_batch(A, np.triu(tla.from_device_cm(dA))).max() <= 1e-13
+
+
+@pytest.mark.parametrize("op", ["potrf", "trsyl", "trlyap"])
+def test_largest_size_1024_against_oracle(h, orc, op):
+    # n = 1024 (the largest size of the benchmark's large-size workload), one
+    # instance per operation through the default plan, element-wise against
+    # the oracle
+    n = 1024
+    print(f"{op} n={n}", flush=True)
+    if op == "potrf":
+        A = I.potrf_problem("large1024", n, 1)
+        dA = tla.to_device_cm(np.triu(A))
+        ops = tla.potrf(h, dA)
+        torch.cuda.synchronize()
+        X = np.triu(tla.from_device_cm(dA))
+        Xr, ir = orc.potrf_batch(A)
+        eta = orc.eta_potrf_batch(A, X)
+    elif op == "trsyl":
+        L, U, C = I.trsyl_problem("large1024", n, 1)
+        dL, dU, dC = tla.to_device_cm(L), tla.to_device_cm(U), tla.to_device_cm(C)
+        ops = tla.trsyl(h, dL, dU, dC)
+        torch.cuda.synchronize()
+        X = tla.from_device_cm(dC)
+        Xr, ir = orc.trsyl_batch(L, U, C)
+        eta = orc.eta_trsyl_batch(L, U, C, X)
+    else:
+        L, S = I.trlyap_problem("large1024", n, 1)
+        dL, dS = tla.to_device_cm(L), tla.to_device_cm(np.tril(S))
+        ops = tla.trlyap(h, dL, dS)
+        torch.cuda.synchronize()
+        X = tla.from_device_cm(dS)
+        Xr, ir = orc.trlyap_batch(L, S)
+        eta = orc.eta_trlyap_batch(L, S, X)
+        assert np.array_equal(X, np.swapaxes(X, 1, 2))
+    assert np.all(ops.info.cpu().numpy() == ir) and np.all(ir == 0)
+    assert rel_err(X, Xr).max() <= 1e-12
+    # element-wise: every entry within 1e-12 of the largest entry of its column
+    colmax = np.abs(Xr).max(axis=1, keepdims=True)
+    assert np.max(np.abs(X - Xr) / np.where(colmax == 0, 1.0, colmax)) <= 1e-12
+    assert eta.max() <= 1e-13

@@ -224,6 +224,26 @@ def test_mixed_large_n_placements(h, orc, op, n):
 
 
 @pytest.mark.parametrize("op", ["potrf", "trsyl", "trlyap"])
+@pytest.mark.parametrize("prec", MIXED)
+@pytest.mark.parametrize("kappa", [1e2, 1e6])
+def test_mixed_n128_condition_grid(h, orc, op, prec, kappa):
+    # the mixed configuration's largest size at both ends of its condition
+    # range, every mixed precision: converged or solved again in FP64, and
+    # within the gate either way
+    n = 128
+    print(f"mixed n=128 {op} {prec} kappa={kappa:g}", flush=True)
+    mats = problem(op, n, 4, kappa, tag="grid128")
+    X, ops = solve(h, op, mats, prec)
+    Xr, ir, eta_fn = oracle_solve(orc, op, mats)
+    st = tla.stat_view(ops.stat)
+    assert np.all(ops.info.cpu().numpy() == ir)
+    assert eta_fn(*mats, X).max() <= 1e-12, st
+    assert rel_err(X, Xr).max() <= fwd_tol(n, kappa)
+    ok = (st["flags"] & tla.STAT_CONVERGED) | (st["flags"] & (tla.STAT_FALLBACK | tla.STAT_BREAKDOWN))
+    assert np.all(ok != 0)
+
+
+@pytest.mark.parametrize("op", ["potrf", "trsyl", "trlyap"])
 def test_second_pass_fallback_matches_fp64(h, orc, op):
     n = 128
     mats = problem(op, n, 4, 1e2, tag="fb128")
