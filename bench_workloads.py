@@ -286,16 +286,22 @@ def planner(a):
     import tempfile
     import paper_1906_08613_amd as tla
     h = tla.Handle(0)
+    ops = ["potrf", "trsyl", "trlyap"]
     ns = list(range(3, 129, 5))
+    # above n = 128 only FP64 exists and only the variant selects a kernel
+    ns_large = [160, 192, 224, 288, 320, 384, 448]
     t0 = time.perf_counter()
-    h.tune(["potrf", "trsyl", "trlyap"], ns, ["f64", "mixed_f32"], batch=1024, reps=2)
+    h.tune(ops, ns, ["f64", "mixed_f32"], batch=1024, reps=2)
+    h.tune(ops, ns_large, ["f64"], batch=256, reps=2)
     t_tune = time.perf_counter() - t0
     path = os.path.join(tempfile.mkdtemp(), "table.txt")
     h.save_table(path)
-    rec = np.loadtxt(path, comments="#")
-    times = {}
-    for r in rec:
-        times[(int(r[0]), int(r[1]), int(r[2]), tuple(int(x) for x in r[4:9]))] = r[9]
+
+    def load(p):
+        rec = np.loadtxt(p, comments="#")
+        return {(int(r[0]), int(r[1]), int(r[2]), tuple(int(x) for x in r[4:9])): r[9] for r in rec}
+
+    times = load(path)
     held = [n for n in ns if n % 7 == 0]
     t0 = time.perf_counter()
     hm = tla.Handle(0)
@@ -305,26 +311,55 @@ def planner(a):
     hu = tla.Handle(0)
     hu.load_table(path)
     hu.mlp_train(epochs=0, lr=3e-3, seed=5, exclude_mod=7)
+    # the large evaluation sizes, never seen in training: measured separately
+    eval_large = [256, 512, 1024]
+    he = tla.Handle(0)
+    he.tune(ops, eval_large, ["f64"], batch=256, reps=2)
+    path_e = os.path.join(tempfile.mkdtemp(), "table_large.txt")
+    he.save_table(path_e)
+    times_e = load(path_e)
 
-    def regret(handle, mode):
+    def regret(handle, mode, table, sizes, precs, batch, by_variant=False):
         handle.set_picker(mode)
         out = []
         for op in range(3):
-            for prec in (0, 1):
-                for n in held:
-                    cand = {k[3]: v for k, v in times.items() if k[0] == op and k[1] == n and k[2] == prec}
+            for prec in precs:
+                for n in sizes:
+                    cand = {k[3]: v for k, v in table.items() if k[0] == op and k[1] == n and k[2] == prec}
                     best = min(cand.values())
-                    pick = handle.get_plan(op, n, prec, 1024).astuple()
-                    out.append(cand.get(tuple(pick), np.inf) / best - 1.0)
+                    pick = handle.get_plan(op, n, prec, batch).astuple()
+                    if by_variant:  # one measured plan per variant above n = 128
+                        t = min(v for k, v in cand.items() if k[0] == pick[0])
+                    else:
+                        t = cand.get(tuple(pick), np.inf)
+                    out.append(t / best - 1.0)
         return np.array(out)
 
-    r_mlp, r_untrained, r_default = regret(hm, tla.PICK_MLP), regret(hu, tla.PICK_MLP), regret(hu, tla.PICK_DEFAULT)
-    print(json.dumps({"workload": "planner: autotuner n=3..128 step 5, f64 + mixed_f32, batch 1024; MLP trained "
-                                  "without n % 7 == 0", "held_out_n": held, "records": len(times),
-                      "tune_seconds": t_tune, "train_seconds": t_train, "train_loss": loss,
+    hm.set_picker_judge(0.0, 0)
+    r_mlp = regret(hm, tla.PICK_MLP, times, held, (0, 1), 1024)
+    r_mlp_large = regret(hm, tla.PICK_MLP, times_e, eval_large, (0,), 256, True)
+    hm.set_picker_judge(0.10, 4)
+    r_judged = regret(hm, tla.PICK_MLP, times, held, (0, 1), 1024)
+    r_judged_large = regret(hm, tla.PICK_MLP, times_e, eval_large, (0,), 256, True)
+    judged, mispredicted = hm.picker_judge_stats()
+    r_untrained = regret(hu, tla.PICK_MLP, times, held, (0, 1), 1024)
+    r_default = regret(hu, tla.PICK_DEFAULT, times, held, (0, 1), 1024)
+    r_default_large = regret(hu, tla.PICK_DEFAULT, times_e, eval_large, (0,), 256, True)
+    print(json.dumps({"workload": "planner: autotuner n=3..128 step 5 (f64 + mixed_f32, batch 1024) and "
+                                  "n=160..448 (f64, batch 256); MLP trained without n % 7 == 0; evaluated on the "
+                                  "held-out n and on n = 256, 512, 1024 (f64, batch 256, not trained on)",
+                      "held_out_n": held, "records": len(times), "tune_seconds": t_tune, "train_seconds": t_train,
+                      "train_loss": loss,
                       "regret_mlp_mean": float(r_mlp.mean()), "regret_mlp_max": float(r_mlp.max()),
+                      "regret_mlp_judged_mean": float(r_judged.mean()),
+                      "regret_mlp_judged_max": float(r_judged.max()),
+                      "judge_timed_picks": judged, "judge_mispredictions": mispredicted,
                       "regret_untrained_mean": float(r_untrained.mean()),
-                      "regret_default_plan_mean": float(r_default.mean())}))
+                      "regret_default_plan_mean": float(r_default.mean()),
+                      "large_n": eval_large,
+                      "regret_mlp_large": [round(float(x), 4) for x in r_mlp_large],
+                      "regret_mlp_judged_large": [round(float(x), 4) for x in r_judged_large],
+                      "regret_default_plan_large": [round(float(x), 4) for x in r_default_large]}))
 
 
 def potrs(a):

@@ -238,7 +238,9 @@ tla_status tla_set_picker(tla_handle h, tla_picker mode);
  * candidate -- the model-based replacement of autotuning that the paper lists
  * as future work (Limitations and future work paragraph).  It is trained on
  * the GPU, by the library's own forward/backward/Adam kernels, on the
- * measurements in the handle's tuning table; the table remains the fallback.
+ * measurements in the handle's tuning table; the table remains the fallback,
+ * also at sizes outside those the network was trained on (per operation and
+ * precision; a network set or loaded from a file covers every size).
  * Parameters are one flat FP32 array (W1[64][F], b1[64], W2[64][64], b2[64],
  * w3[64], b3), F = tla_mlp_num_features().  Host arrays; calls synchronise. */
 int tla_mlp_num_params(void);
@@ -264,6 +266,21 @@ tla_status tla_mlp_predict(tla_handle h, tla_op op, int n, tla_prec prec, int ba
                            double *seconds);
 tla_status tla_mlp_save(tla_handle h, const char *path);
 tla_status tla_mlp_load(tla_handle h, const char *path);
+/* The measured autotuner as the fallback and judge of the learned picker:
+ * when the network's predicted times of its best candidates lie within a
+ * factor (1 + margin) of the best prediction, the picker times those
+ * candidates (at most max_timed, best predicted first, on synthetic inputs of
+ * the query's op, n, precision and batch, with the autotuner's timer) instead
+ * of trusting the network, adds the measurements to the tuning records, keeps
+ * the measured winner for that (op, n, precision) and counts a misprediction
+ * when the winner is not the network's first choice.  The first pick of such
+ * a key is then synchronous.  margin 0 or max_timed < 2 turns the judge off;
+ * the default is margin 0.10, max_timed 4.  Setting it (or retraining or
+ * loading the network) forgets the kept winners.  Host call. */
+tla_status tla_set_picker_judge(tla_handle h, double margin, int max_timed);
+/* Picks the judge has timed since the handle was created, and how many of
+ * them the network had mispredicted.  Host memory. */
+tla_status tla_picker_judge_stats(tla_handle h, int *judged, int *mispredicted);
 
 /* ---------------------------------------------------------- refinement */
 /* Refinement tolerance on the backward error eta (default 1e-13) and the

@@ -38,7 +38,7 @@ SYMBOLS = [
     "tla_set_refine", "tla_status_string",
     "tla_mlp_num_params", "tla_mlp_num_features", "tla_mlp_features", "tla_mlp_set_params",
     "tla_mlp_get_params", "tla_mlp_forward_backward", "tla_mlp_adam_step", "tla_mlp_train",
-    "tla_mlp_predict", "tla_mlp_save", "tla_mlp_load",
+    "tla_mlp_predict", "tla_mlp_save", "tla_mlp_load", "tla_set_picker_judge", "tla_picker_judge_stats",
 ]
 
 
@@ -119,6 +119,8 @@ def lib():
             "tla_mlp_train": (I, [V, I, ctypes.c_float, ctypes.c_ulonglong, I, P]),
             "tla_mlp_predict": (I, [V, I, I, I, I, ctypes.POINTER(Plan), ctypes.POINTER(D)]),
             "tla_mlp_save": (I, [V, ctypes.c_char_p]),
+            "tla_set_picker_judge": (I, [V, D, I]),
+            "tla_picker_judge_stats": (I, [V, ctypes.POINTER(I), ctypes.POINTER(I)]),
             "tla_mlp_load": (I, [V, ctypes.c_char_p]),
         }
         for name, (res, args) in sig.items():
@@ -296,6 +298,14 @@ class Handle:
 
     def mlp_load(self, path):
         check(lib().tla_mlp_load(self.h, path.encode()), "tla_mlp_load")
+
+    def set_picker_judge(self, margin, max_timed=4):
+        check(lib().tla_set_picker_judge(self.h, float(margin), int(max_timed)), "tla_set_picker_judge")
+
+    def picker_judge_stats(self):
+        j, m = ctypes.c_int(0), ctypes.c_int(0)
+        check(lib().tla_picker_judge_stats(self.h, ctypes.byref(j), ctypes.byref(m)), "tla_picker_judge_stats")
+        return j.value, m.value
 
     def save_table(self, path):
         check(lib().tla_save_table(self.h, path.encode()), "tla_save_table")

@@ -47,6 +47,13 @@ struct tla_ctx {
   // refinement settings change, or the tuning table / picker changes.
   // Cached graphs from an older generation are dropped before any replay.
   unsigned long long gen = 0;
+  // The measured autotuner as the judge of the learned picker: predictions
+  // within a factor (1 + judge_margin) of the best one are timed (at most
+  // judge_max of them) and the measured winner is kept per (op, n, prec).
+  double judge_margin = 0.10;
+  int judge_max = 4;
+  int judged = 0, mispredicted = 0;
+  std::map<long long, tla_plan> judged_plans;     // key (op, n, prec) -> measured winner
   void release();
 };
 
@@ -54,6 +61,10 @@ namespace tla {
 inline long long table_key(int op, int n, int prec) { return ((long long)op * 16 + prec) * 100000 + n; }
 bool table_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* p);
 bool mlp_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* p);
+// Times `count` plans of (op, n, prec) on synthetic inputs of `batch`
+// instances (the autotuner's timer, synchronous) into sec[]; an unsupported
+// plan gets +infinity.
+tla_status judge_time(tla_ctx* h, int op, int n, int prec, int batch, const tla_plan* plans, int count, double* sec);
 void mlp_release(tla_ctx* h);
 void ragged_release(tla_ctx* h);
 // Per-device set-up of the allocation-free ragged path (tla_ragged.hip).

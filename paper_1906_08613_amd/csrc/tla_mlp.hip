@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -33,6 +34,14 @@ struct MlpState {
   int step = 0;
   bool trained = false;
   double y_mean = 0.0, y_std = 1.0;  // standardisation of log seconds
+  // sizes the network was trained on, per (op, precision): outside them the
+  // picker does not extrapolate and leaves the choice to the measured table
+  // (or the default plan); a loaded or set network covers every size
+  int n_lo[3][4], n_hi[3][4];
+  void cover_all() {
+    for (int o = 0; o < 3; ++o)
+      for (int p = 0; p < 4; ++p) { n_lo[o][p] = 0; n_hi[o][p] = INT_MAX; }
+  }
   // scratch for a batch of samples
   float *X = nullptr, *T = nullptr, *Y = nullptr, *H1 = nullptr, *H2 = nullptr, *loss = nullptr;
   int cap = 0;
@@ -143,6 +152,7 @@ static tla_status mlp_alloc(tla_ctx* h) {
   if (h->mlp) return TLA_OK;
   MlpState* m = new (std::nothrow) MlpState();
   if (!m) return TLA_E_NOMEM;
+  m->cover_all();
   const size_t b = kMlpParams * sizeof(float);
   if (hipMalloc(&m->P, b) != hipSuccess || hipMalloc(&m->G, b) != hipSuccess || hipMalloc(&m->M, b) != hipSuccess ||
       hipMalloc(&m->V, b) != hipSuccess || hipMalloc(&m->loss, sizeof(float)) != hipSuccess) {
@@ -220,6 +230,10 @@ static tla_status mlp_reset(tla_ctx* h, unsigned long long seed) {
 bool mlp_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* best) {
   MlpState* m = h->mlp;
   if (!m || !m->trained) return false;
+  if (op < 0 || op > 2 || prec < 0 || prec > 3 || n < m->n_lo[op][prec] || n > m->n_hi[op][prec]) return false;
+  // a key the judge has already measured keeps its measured winner
+  const auto jp = h->judged_plans.find(table_key(op, n, prec));
+  if (jp != h->judged_plans.end()) { *best = jp->second; return true; }
   const int nc = num_candidates(op);
   if (mlp_reserve(m, nc) != TLA_OK) return false;
   std::vector<float> X((size_t)nc * kMlpIn);
@@ -247,6 +261,28 @@ bool mlp_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* best) {
     return false;
   const int arg = (int)(std::min_element(Y.begin(), Y.end()) - Y.begin());
   *best = plans[arg];
+  if (h->judge_margin <= 0.0 || h->judge_max < 2) return true;
+  // The judge: candidates predicted within a factor (1 + margin) of the best
+  // prediction (in standardised log seconds: y_std * dy <= log(1 + margin)),
+  // best first, are timed; the measured winner is kept for this key, and the
+  // network's first choice losing counts as a misprediction.
+  std::vector<int> order(usable);
+  for (int i = 0; i < usable; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return Y[a] < Y[b]; });
+  const double win = std::log1p(h->judge_margin) / std::max(m->y_std, 1e-12);
+  std::vector<tla_plan> close;
+  for (int k = 0; k < usable && (int)close.size() < h->judge_max; ++k)
+    if ((double)Y[order[k]] - (double)Y[order[0]] <= win) close.push_back(plans[order[k]]);
+  if (close.size() < 2) return true;
+  std::vector<double> sec(close.size());
+  if (judge_time(h, op, n, prec, batch, close.data(), (int)close.size(), sec.data()) != TLA_OK) return true;
+  const int w = (int)(std::min_element(sec.begin(), sec.end()) - sec.begin());
+  if (!std::isfinite(sec[w])) return true;
+  ++h->judged;
+  if (w != 0) ++h->mispredicted;
+  *best = close[w];
+  h->judged_plans[table_key(op, n, prec)] = close[w];
+  ++h->gen;
   return true;
 }
 
@@ -283,6 +319,7 @@ extern "C" tla_status tla_mlp_set_params(tla_handle h, const float* params) {
   hipMemcpy(h->mlp->M, z.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice);
   hipMemcpy(h->mlp->V, z.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice);
   h->mlp->step = 0;
+  h->mlp->cover_all();
   return TLA_OK;
 }
 
@@ -336,9 +373,16 @@ extern "C" tla_status tla_mlp_train(tla_handle h, int epochs, float lr, unsigned
   MlpState* m = h->mlp;
   std::vector<float> X, T;
   std::vector<double> ly;
+  int lo[3][4], hi[3][4];
+  for (int o = 0; o < 3; ++o)
+    for (int p = 0; p < 4; ++p) { lo[o][p] = INT_MAX; hi[o][p] = -1; }
   for (const TuneRecord& r : h->records) {
     if (exclude_mod > 0 && r.n % exclude_mod == 0) continue;
     if (!(r.seconds > 0.0)) continue;
+    if (r.op >= 0 && r.op < 3 && r.prec >= 0 && r.prec < 4) {
+      lo[r.op][r.prec] = std::min(lo[r.op][r.prec], r.n);
+      hi[r.op][r.prec] = std::max(hi[r.op][r.prec], r.n);
+    }
     std::vector<float> f(kMlpIn);
     mlp_features(r.op, r.n, r.prec, r.batch, r.plan, f.data());
     X.insert(X.end(), f.begin(), f.end());
@@ -374,6 +418,9 @@ extern "C" tla_status tla_mlp_train(tla_handle h, int epochs, float lr, unsigned
   if (final_loss && hipMemcpy(final_loss, m->loss, sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
     return TLA_E_HIP;
   m->trained = true;
+  for (int o = 0; o < 3; ++o)
+    for (int p = 0; p < 4; ++p) { m->n_lo[o][p] = lo[o][p]; m->n_hi[o][p] = hi[o][p]; }
+  h->judged_plans.clear();  // the judge's verdicts were on the previous network
   return TLA_OK;
 }
 
@@ -428,5 +475,22 @@ extern "C" tla_status tla_mlp_load(tla_handle h, const char* path) {
   h->mlp->y_mean = mu;
   h->mlp->y_std = sd;
   h->mlp->trained = true;
+  h->judged_plans.clear();
+  return TLA_OK;
+}
+
+extern "C" tla_status tla_set_picker_judge(tla_handle h, double margin, int max_timed) {
+  if (!h || !(margin >= 0.0) || max_timed < 0) return TLA_E_ARG;
+  h->judge_margin = margin;
+  h->judge_max = max_timed;
+  h->judged_plans.clear();
+  ++h->gen;
+  return TLA_OK;
+}
+
+extern "C" tla_status tla_picker_judge_stats(tla_handle h, int* judged, int* mispredicted) {
+  if (!h || !judged || !mispredicted) return TLA_E_ARG;
+  *judged = h->judged;
+  *mispredicted = h->mispredicted;
   return TLA_OK;
 }

@@ -24,9 +24,9 @@ namespace tla {
 // trsyl/trlyap 0 = coefficients and solution in LDS, 1 = coefficients read
 // through the caches, 2 = solution in the global workspace as well.
 KFn potrf_mixed_kernel(int prec, int var, int te, int nwi, int placement);
-// FP32 work matrices and the FP64 solution in the workspace (placement 3 and
-// the large sizes); 16 x 16 matrix-core tiles in the type named by prec;
-// nwi 0..3 = 1, 2, 4, 16 waves.
+// FP32 work matrices and the FP64 solution in the workspace (placement 3, n up
+// to 128); 16 x 16 matrix-core tiles in the type named by prec;
+// nwi 0..2 = 1, 2, 4 waves.
 KFn potrf_mixed_ws_kernel(int prec, int var, int nwi);
 KFn trsyl_mixed_ws_kernel(int prec, int var, int nwi);
 KFn trlyap_mixed_ws_kernel(int prec, int var, int nwi);

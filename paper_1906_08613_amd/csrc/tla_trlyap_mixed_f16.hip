@@ -27,23 +27,23 @@ KFn trlyap_mixed_kernel_f16(int var, int te, int nwi, int pl) {
     return nullptr;
   return tab[((var * kNumTE + te) * kNumNW + nwi) * kPL + pl];
 }
-// Work matrices in the workspace (placement 3, and the sizes above the
-// LDS-resident ones): 16 x 16 tiles on the matrix cores, waves 1 / 2 / 4 / 16.
+// Work matrices in the workspace (placement 3, sizes up to the
+// LDS-resident ones): 16 x 16 tiles on the matrix cores, waves 1 / 2 / 4.
 namespace {
 template <int VAR, int NWI>
 void fill_ws(KFn* tab) {
-  constexpr int NW = NWI == 0 ? 1 : (NWI == 1 ? 2 : (NWI == 2 ? 4 : 16));
-  tab[VAR * 4 + NWI] = reinterpret_cast<KFn>(&k_trlyap_mixed<16, ENG_MFMA_F16, NW, VAR, false, true, true>);
-  if constexpr (NWI + 1 < 4) fill_ws<VAR, NWI + 1>(tab);
+  constexpr int NW = NWI == 0 ? 1 : (NWI == 1 ? 2 : 4);
+  tab[VAR * 3 + NWI] = reinterpret_cast<KFn>(&k_trlyap_mixed<16, ENG_MFMA_F16, NW, VAR, false, true, true>);
+  if constexpr (NWI + 1 < 3) fill_ws<VAR, NWI + 1>(tab);
   else if constexpr (VAR + 1 < LYA_NVAR) fill_ws<VAR + 1, 0>(tab);
 }
 }  // namespace
 
 KFn trlyap_mixed_ws_kernel_f16(int var, int nwi) {
-  static KFn tab[LYA_NVAR * 4] = {};
+  static KFn tab[LYA_NVAR * 3] = {};
   static bool init = false;
   if (!init) { fill_ws<0, 0>(tab); init = true; }
-  if (var < 0 || var >= LYA_NVAR || nwi < 0 || nwi >= 4) return nullptr;
-  return tab[var * 4 + nwi];
+  if (var < 0 || var >= LYA_NVAR || nwi < 0 || nwi >= 3) return nullptr;
+  return tab[var * 3 + nwi];
 }
 }  // namespace tla

@@ -136,6 +136,27 @@ tla_status time_plan(tla_ctx* h, Bench& B, int op, int prec, const tla_plan& p, 
 
 }  // namespace
 
+namespace tla {
+tla_status judge_time(tla_ctx* h, int op, int n, int prec, int batch, const tla_plan* plans, int count, double* sec) {
+  if (hipSetDevice(h->device) != hipSuccess) return TLA_E_HIP;
+  Bench B;
+  tla_status st = make_bench(B, op, n, batch, h->stream);
+  if (st != TLA_OK) return st;
+  for (int i = 0; i < count; ++i) {
+    sec[i] = INFINITY;
+    double t = 0.0;
+    const tla_status s = time_plan(h, B, op, prec, plans[i], 2, &t);
+    if (s == TLA_OK) {
+      sec[i] = t;
+      h->records.push_back({op, n, prec, batch, plans[i], t});
+    } else if (s != TLA_E_UNSUPPORTED) {
+      return s;
+    }
+  }
+  return TLA_OK;
+}
+}  // namespace tla
+
 extern "C" tla_status tla_time_plan(tla_handle h, tla_op op, int n, tla_prec prec, int batch, const tla_plan* plan,
                                     int reps, double* seconds) {
   if (!h || !plan || !seconds || n < 1 || n > kMaxLargeN || batch < 1 || reps < 1 || op < 0 || op > 2) return TLA_E_ARG;
@@ -165,7 +186,7 @@ extern "C" tla_status tla_tune(tla_handle h, int n_ops, const int* ops, int n_ns
         const int prec = precs[ip];
         double best = INFINITY;
         tla_plan bp{};
-        bool seen[8] = {false, false, false, false, false, false, false, false};
+        bool seen[16] = {};  // by variant index (at most 9 variants)
         for (int c = 0; c < num_candidates(op); ++c) {
           tla_plan p;
           candidate(op, c, &p);

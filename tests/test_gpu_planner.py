@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import paper_1906_08613_amd as tla
+from paper_1906_08613_amd import inputs as I
 from oracle import mlp_ref as M
 
 pytestmark = pytest.mark.gpu
@@ -137,6 +138,60 @@ def test_mlp_regret_on_measured_timings(h, tmp_path):
     r_default = regret(untrained, tla.PICK_DEFAULT)
     print("regret trained", r_trained, "untrained", r_untrained, "default", r_default, flush=True)
     assert r_trained.mean() < r_untrained.mean()
+    # the learned picker (with its measured judge) does at least as well as the built-in default plan
+    assert r_trained.mean() <= r_default.mean()
     assert r_trained.mean() <= 0.5
     for hd in (ht, trained, untrained):
         hd.close()
+
+
+def test_judge_times_close_predictions(h, tmp_path):
+    # a network trained on a toy table whose costs differ only by the variant:
+    # with a wide margin the picker times its best predictions and keeps the
+    # measured winner; with the judge off it only predicts
+    path = str(tmp_path / "t3.txt")
+    synthetic_table(path, toy_time)
+    hj = tla.Handle(0)
+    hj.load_table(path)
+    hj.mlp_train(epochs=300, lr=3e-3, seed=3, exclude_mod=0)
+    hj.set_picker(tla.PICK_MLP)
+    hj.set_picker_judge(0.0, 4)
+    p_off = hj.get_plan("trsyl", 40, "f64", 256).astuple()
+    assert hj.picker_judge_stats() == (0, 0)
+    hj.set_picker_judge(100.0, 3)
+    n_records = len(open(path).read().splitlines())
+    p_on = hj.get_plan("trsyl", 40, "f64", 256).astuple()
+    judged, mis = hj.picker_judge_stats()
+    assert judged == 1 and 0 <= mis <= 1
+    # the network's first choice is the judged winner unless it was mispredicted
+    assert (p_on == p_off) == (mis == 0)
+    # the three timings joined the tuning records; the verdict is kept (no second timing)
+    out = str(tmp_path / "t3b.txt")
+    hj.save_table(out)
+    assert len(open(out).read().splitlines()) == n_records + 3
+    assert hj.get_plan("trsyl", 40, "f64", 256).astuple() == p_on
+    assert hj.picker_judge_stats() == (1, mis)
+    # a plan the judge keeps runs
+    L, U, C = I.trsyl_problem("judge", 40, 4)
+    dL, dU, dC = tla.to_device_cm(L), tla.to_device_cm(U), tla.to_device_cm(C)
+    ops = tla.trsyl(hj, dL, dU, dC)
+    torch.cuda.synchronize()
+    assert np.all(ops.info.cpu().numpy() == 0)
+    hj.close()
+
+
+def test_mlp_does_not_extrapolate_in_n(h, tmp_path):
+    # trained on n = 4..128: at n = 200 the learned picker leaves the choice
+    # to the measured table (its nearest tuned size), inside it predicts
+    path = str(tmp_path / "t4.txt")
+    synthetic_table(path, toy_time)
+    hx = tla.Handle(0)
+    hx.load_table(path)
+    hx.mlp_train(epochs=200, lr=3e-3, seed=4, exclude_mod=0)
+    hx.set_picker_judge(0.0, 0)
+    for op in range(3):
+        hx.set_picker(tla.PICK_TABLE)
+        table_pick = hx.get_plan(op, 200, "f64", 1024).astuple()
+        hx.set_picker(tla.PICK_MLP)
+        assert hx.get_plan(op, 200, "f64", 1024).astuple() == table_pick
+    hx.close()
