@@ -1,5 +1,5 @@
 """The benchmark's secondary workloads (one JSON line each), run with
-python bench.py --workload {potrf16,sweep,ragged,large,planner,potrs,variants,plan}.
+python bench.py --workload {potrf16,sweep,ragged,large,planner,potrs,variants,plan,exact}.
 
 potrf16 : FP64 Cholesky, 1024 instances at n = 16, replayed many times inside
           one HIP graph (the batch is too small to fill the GPU by itself).
@@ -15,6 +15,8 @@ potrs   : solve with the Cholesky factor, FP64, n = 64, 16 right-hand sides,
 variants: best time of each blocked-algorithm variant (over tiles, engines,
           waves and placements), FP64, n = 16 .. 1024: 4096 instances up to
           n = 128, 256 above (one in-place plan per variant there).
+exact   : exact-size kernels (compiled at run time for each n) against the
+          ahead-of-time kernels of the same plan, FP64, n = 4..128.
 plan    : one operation (first of --ops) at --n, --batch, --prec with the plan
           given by --plan, timed by the library's own timer (for profiling
           one kernel).
@@ -362,6 +364,73 @@ def planner(a):
                       "regret_default_plan_large": [round(float(x), 4) for x in r_default_large]}))
 
 
+def exact(a):
+    """Exact-size kernels (compiled at run time for each n) against the
+    ahead-of-time in-place kernels of the same plan, FP64."""
+    import torch
+    import paper_1906_08613_amd as tla
+    from paper_1906_08613_amd import inputs as I
+    h = tla.Handle(0)
+    batch = 4096
+    rows = []
+    for op in ("potrf", "trsyl", "trlyap"):
+        for n in (4, 8, 12, 16, 24, 32, 48, 64, 96, 128):
+            if op == "potrf":
+                mats = (np.triu(I.potrf_problem("exact", n, batch)),)
+            elif op == "trsyl":
+                mats = I.trsyl_problem("exact", n, batch)
+            else:
+                L, S = I.trlyap_problem("exact", n, batch)
+                mats = (L, np.tril(S))
+            dev = [tla.to_device_cm(m) for m in mats]
+            pristine = dev[-1].clone()
+            ops = tla.Operands(n, *dev)
+
+            def run():
+                dev[-1].copy_(pristine)
+                if op == "potrf":
+                    h.potrf_batched("f64", batch, n, ops.n, ops.ptrs[0], ops.lds[0], ops.info, ops.stat)
+                elif op == "trsyl":
+                    h.trsyl_batched("f64", batch, n, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1],
+                                    ops.ptrs[2], ops.lds[2], ops.info, ops.stat)
+                else:
+                    h.trlyap_batched("f64", batch, n, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1],
+                                     ops.info, ops.stat)
+
+            def timed(reps=7):
+                run()
+                torch.cuda.synchronize()
+                ts, tc = [], []
+                for _ in range(reps):
+                    e0, e1 = _events(torch)
+                    e2, e3 = _events(torch)
+                    e2.record()
+                    dev[-1].copy_(pristine)
+                    e3.record()
+                    e0.record()
+                    run()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ts.append(e2.elapsed_time(e1) * 1e-3)
+                    tc.append(e2.elapsed_time(e3) * 1e-3)
+                return float(np.median(ts) - np.median(tc))
+
+            h.set_exact_size(False)
+            tg = timed()
+            h.set_exact_size(True)
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            t_compile = time.perf_counter() - t0
+            te = timed()
+            h.set_exact_size(False)
+            rows.append({"op": op, "n": n, "generic_us": round(tg * 1e6, 1), "exact_us": round(te * 1e6, 1),
+                         "speedup": round(tg / te, 3), "first_call_s": round(t_compile, 2)})
+            print(json.dumps(rows[-1]), flush=True)
+    print(json.dumps({"workload": f"exact-size kernels vs ahead-of-time, FP64, {batch} instances, default plans",
+                      "rows": rows, "compiled": h.exact_size_stats()[0]}))
+
+
 def potrs(a):
     import torch
     import oracle
@@ -446,4 +515,4 @@ def variants(a):
 
 def run(a):
     {"potrf16": potrf16, "sweep": sweep, "ragged": ragged, "large": large, "planner": planner,
-     "potrs": potrs, "variants": variants, "plan": plan}[a.workload](a)
+     "potrs": potrs, "variants": variants, "plan": plan, "exact": exact}[a.workload](a)

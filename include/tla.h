@@ -187,6 +187,22 @@ tla_status tla_ragged_batched(tla_handle h, tla_prec prec, int batch, int n_max,
 tla_status tla_ragged_batched_noalloc(tla_handle h, tla_prec prec, int batch, int n_max,
                                       const tla_desc *d, int *info, tla_stat *stat);
 
+/* Exact-size kernels (the paper's routines are generated for each input size,
+ * Preliminary performance results paragraph).  FP64 calls whose plan solves
+ * in place (placement 3, n_max <= 128) can run the same kernel compiled at
+ * run time (hiprtc) for n = n_max as a compile-time constant, cached on the
+ * handle per (op, n, variant, waves); compiling takes about a third of a
+ * second.  Instances with n[b] != n_max take the generic code compiled into
+ * the same kernel.  mode 0: off (default); 1: always; 2: where measured
+ * faster -- the first call of a key times the plan both ways on synthetic
+ * inputs (synchronous, allocates) and keeps the faster for that key.  The
+ * kernel source is the library's headers in the csrc directory next to the
+ * built library (or in the directory named by TLA_KERNEL_DIR); when they are
+ * missing or do not compile, the call uses the ahead-of-time kernel. */
+tla_status tla_set_exact_size(tla_handle h, int mode);
+/* Exact-size kernels compiled so far on the handle, and compilations that failed. */
+tla_status tla_exact_size_stats(tla_handle h, int *compiled, int *failed);
+
 /* ------------------------------------------------------- plans and tuning */
 /* A plan names the kernel that solves one (op, n bucket, precision):
  * variant = blocked-algorithm variant (op specific, see tla_variant_name),

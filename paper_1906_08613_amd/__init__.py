@@ -39,6 +39,7 @@ SYMBOLS = [
     "tla_mlp_num_params", "tla_mlp_num_features", "tla_mlp_features", "tla_mlp_set_params",
     "tla_mlp_get_params", "tla_mlp_forward_backward", "tla_mlp_adam_step", "tla_mlp_train",
     "tla_mlp_predict", "tla_mlp_save", "tla_mlp_load", "tla_set_picker_judge", "tla_picker_judge_stats",
+    "tla_set_exact_size", "tla_exact_size_stats",
 ]
 
 
@@ -120,6 +121,8 @@ def lib():
             "tla_mlp_predict": (I, [V, I, I, I, I, ctypes.POINTER(Plan), ctypes.POINTER(D)]),
             "tla_mlp_save": (I, [V, ctypes.c_char_p]),
             "tla_set_picker_judge": (I, [V, D, I]),
+            "tla_set_exact_size": (I, [V, I]),
+            "tla_exact_size_stats": (I, [V, ctypes.POINTER(I), ctypes.POINTER(I)]),
             "tla_picker_judge_stats": (I, [V, ctypes.POINTER(I), ctypes.POINTER(I)]),
             "tla_mlp_load": (I, [V, ctypes.c_char_p]),
         }
@@ -298,6 +301,15 @@ class Handle:
 
     def mlp_load(self, path):
         check(lib().tla_mlp_load(self.h, path.encode()), "tla_mlp_load")
+
+    def set_exact_size(self, mode):
+        """0 / False: off; 1 / True: always; 2: where measured faster."""
+        check(lib().tla_set_exact_size(self.h, int(mode)), "tla_set_exact_size")
+
+    def exact_size_stats(self):
+        c, f = ctypes.c_int(0), ctypes.c_int(0)
+        check(lib().tla_exact_size_stats(self.h, ctypes.byref(c), ctypes.byref(f)), "tla_exact_size_stats")
+        return c.value, f.value
 
     def set_picker_judge(self, margin, max_timed=4):
         check(lib().tla_set_picker_judge(self.h, float(margin), int(max_timed)), "tla_set_picker_judge")

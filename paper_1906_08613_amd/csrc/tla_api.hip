@@ -389,6 +389,26 @@ tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& 
   if (getenv("TLA_LOG"))
     fprintf(stderr, "tla: op %d prec %d batch %d n_max %d plan(v%d t%d e%d w%d) lds %zu placement %d\n", op, prec,
             a.batch, a.n_max, p.variant, p.tile, p.engine, p.waves, lds, pl);
+  if (prec == TLA_F64 && pl == 3 && h->exact_size) {
+    // the same in-place kernel compiled for this n (falls through when
+    // unavailable); in the measured mode only where it timed faster
+    bool use = h->exact_size == 1;
+    if (h->exact_size == 2) {
+      const long long key = ((long long)(op * 256 + a.n_max) * 16 + p.variant) * 8 + p.waves;
+      auto it = h->exact_choice.find(key);
+      if (it == h->exact_choice.end()) {
+        bool faster = false;
+        tla_status ds = exact_size_decide(h, op, a.n_max, std::min(a.batch, 4096), p, &faster);
+        if (ds != TLA_OK) return ds;
+        it = h->exact_choice.emplace(key, faster).first;
+      }
+      use = it->second;
+    }
+    if (use) {
+      const tla_status js = jit_launch(h, op, p.variant, p.waves, lds, a);
+      if (js != TLA_E_UNSUPPORTED) return js;
+    }
+  }
   tla_status s = launch_one(h, fn, lds, a.batch, p.waves, a);
   if (s != TLA_OK || !xg) return s;
   // second pass: FP64 solve of the instances the mixed kernel left

@@ -21,6 +21,7 @@ struct TuneRecord {
 };
 
 struct MlpState;  // learned cost model (tla_mlp.hip)
+struct JitState;  // exact-size kernels compiled at run time (tla_jit.hip)
 struct RagState;  // ragged batches: work-list buffers and captured graphs (tla_ragged.hip)
 
 }  // namespace tla
@@ -38,6 +39,9 @@ struct tla_ctx {
   std::map<long long, tla_plan> best;             // key (op, n, prec) -> fastest plan
   tla::MlpState* mlp = nullptr;
   tla::RagState* rag = nullptr;
+  tla::JitState* jit = nullptr;
+  int exact_size = 0;                             // exact-size kernels: 0 off, 1 on, 2 where measured faster
+  std::map<long long, bool> exact_choice;         // mode 2: key (op, n, variant, waves) -> measured verdict
   double* work = nullptr;                         // FP64 workspace of the mixed kernels
   size_t work_bytes = 0;
   tla_stat* stat_buf = nullptr;                   // refinement records when the caller passes none
@@ -67,6 +71,14 @@ bool mlp_pick(tla_ctx* h, int op, int n, int prec, int batch, tla_plan* p);
 tla_status judge_time(tla_ctx* h, int op, int n, int prec, int batch, const tla_plan* plans, int count, double* sec);
 void mlp_release(tla_ctx* h);
 void ragged_release(tla_ctx* h);
+void jit_release(tla_ctx* h);
+// Exact-size in-place FP64 kernel of (op, n_max, variant, waves): TLA_OK when
+// launched, TLA_E_UNSUPPORTED (nothing launched) when none can be had.
+tla_status jit_launch(tla_ctx* h, int op, int var, int nw, size_t lds, const KArgs& a);
+// Times plan p of (op, n, FP64) with the exact-size kernels off and on (the
+// autotuner's timer, synthetic inputs); *use_exact when on measured at least
+// 2% faster.
+tla_status exact_size_decide(tla_ctx* h, int op, int n, int batch, const tla_plan& p, bool* use_exact);
 // Per-device set-up of the allocation-free ragged path (tla_ragged.hip).
 tla_status noalloc_init(int device);
 tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& a);

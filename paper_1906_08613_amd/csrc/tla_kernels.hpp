@@ -5,7 +5,14 @@
 // triangles with column-coalesced loads into LDS, runs one blocked variant
 // and writes the referenced part of the result back in place.
 #pragma once
+#ifdef __HIPCC_RTC__
+// (compiled at run time by the exact-size path: no C library headers there)
+#ifndef INT_MAX
+#define INT_MAX __INT_MAX__
+#endif
+#else
 #include <climits>
+#endif
 
 #include "tla_solvers.hpp"
 #include "tla_internal.h"

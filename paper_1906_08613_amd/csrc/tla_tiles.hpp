@@ -14,7 +14,9 @@
 // A operand (16 x K slice): lane l holds A[l&15][k-block(l>>4)];
 // B operand (K x 16 slice): lane l holds B[k-block(l>>4)][l&15].
 #pragma once
+#ifndef __HIPCC_RTC__  // (the run-time compiler provides the HIP device API itself)
 #include <hip/hip_runtime.h>
+#endif
 #include <stdint.h>
 
 #include <type_traits>

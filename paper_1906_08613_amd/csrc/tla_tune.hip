@@ -137,6 +137,24 @@ tla_status time_plan(tla_ctx* h, Bench& B, int op, int prec, const tla_plan& p, 
 }  // namespace
 
 namespace tla {
+tla_status exact_size_decide(tla_ctx* h, int op, int n, int batch, const tla_plan& p, bool* use_exact) {
+  *use_exact = false;
+  Bench B;
+  tla_status st = make_bench(B, op, n, batch, h->stream);
+  if (st != TLA_OK) return st;
+  const int saved = h->exact_size;
+  double tg = 0.0, te = 0.0;
+  h->exact_size = 0;
+  st = time_plan(h, B, op, TLA_F64, p, 3, &tg);
+  if (st == TLA_OK) {
+    h->exact_size = 1;
+    st = time_plan(h, B, op, TLA_F64, p, 3, &te);
+  }
+  h->exact_size = saved;
+  if (st == TLA_OK) *use_exact = te < 0.98 * tg;
+  return st;
+}
+
 tla_status judge_time(tla_ctx* h, int op, int n, int prec, int batch, const tla_plan* plans, int count, double* sec) {
   if (hipSetDevice(h->device) != hipSuccess) return TLA_E_HIP;
   Bench B;
@@ -269,6 +287,7 @@ extern "C" tla_status tla_load_table(tla_handle h, const char* path) {
 void tla_ctx::release() {
   tla::mlp_release(this);
   tla::ragged_release(this);
+  tla::jit_release(this);
   if (work) hipFree(work);
   if (stat_buf) hipFree(stat_buf);
   work = nullptr;
