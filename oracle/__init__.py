@@ -75,6 +75,14 @@ def lib():
             "orc_eta_trlyap_batch": (None, [c_int, c_int, D, D, D, D, c_int]),
             "orc_refine": (c_int, [c_int, c_int, D, D, D, D, c_int, c_double, I, I, D]),
             "orc_max_threads": (c_int, []),
+            "orc_kron_gesyl": (c_int, [c_int, D, c_int, D, c_int, D, c_int, D, c_int, D]),
+            "orc_kron_gelyap": (c_int, [c_int, D, c_int, D, c_int, D, c_int, D]),
+            "orc_eta_gesyl": (c_double, [c_int, D, c_int, D, c_int, D, c_int, D, c_int]),
+            "orc_eta_gelyap": (c_double, [c_int, D, c_int, D, c_int, D, c_int]),
+            "orc_kron_gesyl_batch": (None, [c_int, c_int, D, D, D, D, I, c_int]),
+            "orc_kron_gelyap_batch": (None, [c_int, c_int, D, D, D, I, c_int]),
+            "orc_eta_gesyl_batch": (None, [c_int, c_int, D, D, D, D, D, c_int]),
+            "orc_eta_gelyap_batch": (None, [c_int, c_int, D, D, D, D, c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -291,3 +299,67 @@ def forward_error(X, Xref):
     num = np.sqrt(((X - Xref) ** 2).sum(axis=(-1, -2)))
     den = np.sqrt((Xref ** 2).sum(axis=(-1, -2)))
     return num / np.where(den == 0, 1.0, den)
+
+
+# ------------------------------------------------ general (non-triangular) equations
+def gesyl(A, B, C):
+    """General Sylvester A X + X B = C by its Kronecker system (dense GEPP)."""
+    n = C.shape[-1]
+    a, b, c = _cm(A), _cm(B), _cm(C)
+    x = np.zeros_like(c)
+    w = np.zeros(n ** 4 + n ** 2)
+    st = lib().orc_kron_gesyl(n, _dp(a), n, _dp(b), n, _dp(c), n, _dp(x), n, _dp(w))
+    return _from_cm(x), st
+
+
+def gelyap(A, S):
+    """General Lyapunov A X + X A^T = S (S by its lower triangle) by its Kronecker system."""
+    n = S.shape[-1]
+    a, s = _cm(A), _cm(S)
+    x = np.zeros_like(s)
+    w = np.zeros(n ** 4 + n ** 2)
+    st = lib().orc_kron_gelyap(n, _dp(a), n, _dp(s), n, _dp(x), n, _dp(w))
+    return _from_cm(x), st
+
+
+def eta_gesyl(A, B, C, X):
+    n = C.shape[-1]
+    return lib().orc_eta_gesyl(n, _dp(_cm(A)), n, _dp(_cm(B)), n, _dp(_cm(C)), n, _dp(_cm(X)), n)
+
+
+def eta_gelyap(A, S, X):
+    n = S.shape[-1]
+    return lib().orc_eta_gelyap(n, _dp(_cm(A)), n, _dp(_cm(S)), n, _dp(_cm(X)), n)
+
+
+def gesyl_batch(A, B, C, threads=0):
+    batch, n = C.shape[0], C.shape[-1]
+    a, b, c = _cm(A), _cm(B), _cm(C)
+    x = np.zeros_like(c)
+    info = np.zeros(batch, dtype=np.int32)
+    lib().orc_kron_gesyl_batch(batch, n, _dp(a), _dp(b), _dp(c), _dp(x), _ip(info), threads)
+    return _from_cm(x), info
+
+
+def gelyap_batch(A, S, threads=0):
+    batch, n = S.shape[0], S.shape[-1]
+    a, s = _cm(A), _cm(S)
+    x = np.zeros_like(s)
+    info = np.zeros(batch, dtype=np.int32)
+    lib().orc_kron_gelyap_batch(batch, n, _dp(a), _dp(s), _dp(x), _ip(info), threads)
+    return _from_cm(x), info
+
+
+def eta_gesyl_batch(A, B, C, X, threads=0):
+    batch, n = C.shape[0], C.shape[-1]
+    eta = np.zeros(batch)
+    lib().orc_eta_gesyl_batch(batch, n, _dp(_cm(A)), _dp(_cm(B)), _dp(_cm(C)), _dp(_cm(X)), _dp(eta), threads)
+    return eta
+
+
+def eta_gelyap_batch(A, S, X, threads=0):
+    batch, n = S.shape[0], S.shape[-1]
+    eta = np.zeros(batch)
+    lib().orc_eta_gelyap_batch(batch, n, _dp(_cm(A)), _dp(_cm(S)), _dp(_cm(X)), _dp(eta), threads)
+    return eta
+

@@ -233,7 +233,93 @@ int orc_kron_lyap(int n, const double *L, int ldl, const double *S, int lds,
   return st;
 }
 
+/*
+ * General (non-triangular) Sylvester A X + X B = C and Lyapunov
+ * A X + X A^T = S: the equations of Fig. 2 before any reduction to triangular
+ * form, which the Bartels-Stewart method brings them to (the paper treats only
+ * the triangular cores).  The oracle is the plain definition, the Kronecker
+ * system with column-major vec, solved by the dense elimination above:
+ *   Sylvester: (I (x) A + B^T (x) I) vec X = vec C
+ *   Lyapunov : (I (x) A + A (x) I) vec X = vec S   (S given by its lower triangle)
+ * A and B are read in full.  W must hold n^4 + n^2 doubles.  Returns the GEPP
+ * status (1: the operator is singular to working precision at a pivot).
+ */
+int orc_kron_gesyl(int n, const double *A, int lda, const double *B, int ldb,
+                   const double *C, int ldc, double *X, int ldx, double *W) {
+  int m = n * n;
+  double *M = W, *r = W + (size_t)m * m;
+  memset(M, 0, sizeof(double) * (size_t)m * m);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      int row = i + j * n;
+      for (int p = 0; p < n; ++p) E(M, m, row, p + j * n) += E(A, lda, i, p);  /* (I (x) A)   */
+      for (int q = 0; q < n; ++q) E(M, m, row, i + q * n) += E(B, ldb, q, j);  /* (B^T (x) I) */
+      r[row] = E(C, ldc, i, j);
+    }
+  int st = orc_gepp(m, M, r);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) E(X, ldx, i, j) = r[i + j * n];
+  return st;
+}
+
+int orc_kron_gelyap(int n, const double *A, int lda, const double *S, int lds,
+                    double *X, int ldx, double *W) {
+  int m = n * n;
+  double *M = W, *r = W + (size_t)m * m;
+  memset(M, 0, sizeof(double) * (size_t)m * m);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      int row = i + j * n;
+      for (int p = 0; p < n; ++p) E(M, m, row, p + j * n) += E(A, lda, i, p);  /* A X   */
+      for (int q = 0; q < n; ++q) E(M, m, row, i + q * n) += E(A, lda, j, q);  /* X A^T */
+      r[row] = (i >= j) ? E(S, lds, i, j) : E(S, lds, j, i);
+    }
+  int st = orc_gepp(m, M, r);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) E(X, ldx, i, j) = r[i + j * n];
+  return st;
+}
+
 /* ---- backward and forward error measures (all FP64, Frobenius norms) ---- */
+
+/* General Sylvester: ||C - A X - X B||_F / ((||A||_F + ||B||_F) ||X||_F + ||C||_F),
+ * A and B in full. */
+double orc_eta_gesyl(int n, const double *A, int lda, const double *B, int ldb,
+                     const double *C, int ldc, const double *X, int ldx) {
+  double num = 0.0, na = 0.0, nb = 0.0, nx = 0.0, nc = 0.0;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      double s = E(C, ldc, i, j);
+      for (int k = 0; k < n; ++k) s -= E(A, lda, i, k) * E(X, ldx, k, j);
+      for (int k = 0; k < n; ++k) s -= E(X, ldx, i, k) * E(B, ldb, k, j);
+      num += s * s;
+      na += E(A, lda, i, j) * E(A, lda, i, j);
+      nb += E(B, ldb, i, j) * E(B, ldb, i, j);
+      nx += E(X, ldx, i, j) * E(X, ldx, i, j);
+      nc += E(C, ldc, i, j) * E(C, ldc, i, j);
+    }
+  return sqrt(num) / ((sqrt(na) + sqrt(nb)) * sqrt(nx) + sqrt(nc));
+}
+
+/* General Lyapunov: ||S - A X - X A^T||_F / (2 ||A||_F ||X||_F + ||S||_F),
+ * A in full, S given by its lower triangle, X full. */
+double orc_eta_gelyap(int n, const double *A, int lda, const double *S, int lds,
+                      const double *X, int ldx) {
+  double num = 0.0, na = 0.0, nx = 0.0, ns = 0.0;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      double sv = (i >= j) ? E(S, lds, i, j) : E(S, lds, j, i);
+      double s = sv;
+      for (int k = 0; k < n; ++k) s -= E(A, lda, i, k) * E(X, ldx, k, j);
+      for (int k = 0; k < n; ++k) s -= E(X, ldx, i, k) * E(A, lda, j, k);
+      num += s * s;
+      na += E(A, lda, i, j) * E(A, lda, i, j);
+      nx += E(X, ldx, i, j) * E(X, ldx, i, j);
+      ns += sv * sv;
+    }
+  return sqrt(num) / (2.0 * sqrt(na) * sqrt(nx) + sqrt(ns));
+}
+
 
 /* ||A - X^T X||_F / ||A||_F using the upper triangle of X and the full
  * symmetric A reconstructed from its upper triangle. */
@@ -370,6 +456,52 @@ void orc_eta_trlyap_batch(int batch, int n, const double *L, const double *S, co
 #pragma omp parallel for schedule(dynamic, 4)
   for (int b = 0; b < batch; ++b)
     eta[b] = orc_eta_trlyap(n, L + b * st, n, S + b * st, n, X + b * st, n);
+}
+
+void orc_kron_gesyl_batch(int batch, int n, const double *A, const double *B, const double *C, double *X,
+                          int *info, int threads) {
+  set_threads(threads);
+  size_t st = (size_t)n * n;
+#pragma omp parallel
+  {
+    double *W = (double *)malloc(sizeof(double) * ((size_t)n * n * n * n + (size_t)n * n));
+#pragma omp for schedule(dynamic, 1)
+    for (int b = 0; b < batch; ++b)
+      info[b] = W ? orc_kron_gesyl(n, A + b * st, n, B + b * st, n, C + b * st, n, X + b * st, n, W) : -99;
+    free(W);
+  }
+}
+
+void orc_kron_gelyap_batch(int batch, int n, const double *A, const double *S, double *X, int *info,
+                           int threads) {
+  set_threads(threads);
+  size_t st = (size_t)n * n;
+#pragma omp parallel
+  {
+    double *W = (double *)malloc(sizeof(double) * ((size_t)n * n * n * n + (size_t)n * n));
+#pragma omp for schedule(dynamic, 1)
+    for (int b = 0; b < batch; ++b)
+      info[b] = W ? orc_kron_gelyap(n, A + b * st, n, S + b * st, n, X + b * st, n, W) : -99;
+    free(W);
+  }
+}
+
+void orc_eta_gesyl_batch(int batch, int n, const double *A, const double *B, const double *C,
+                         const double *X, double *eta, int threads) {
+  set_threads(threads);
+  size_t st = (size_t)n * n;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int b = 0; b < batch; ++b)
+    eta[b] = orc_eta_gesyl(n, A + b * st, n, B + b * st, n, C + b * st, n, X + b * st, n);
+}
+
+void orc_eta_gelyap_batch(int batch, int n, const double *A, const double *S, const double *X,
+                          double *eta, int threads) {
+  set_threads(threads);
+  size_t st = (size_t)n * n;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int b = 0; b < batch; ++b)
+    eta[b] = orc_eta_gelyap(n, A + b * st, n, S + b * st, n, X + b * st, n);
 }
 
 /* ------------------------------------------------------------------------
