@@ -36,6 +36,9 @@
  *        trsyl/trlyap: 1 + (i + j*n) of the first zero denominator
  *        l_ii + u_jj (resp. l_ii + l_jj) in column-major order; X unspecified.
  *   -3   (ragged batches only) the descriptor names no known operation
+ *   -4   (general equations only) a coefficient has complex eigenvalues
+ *   -5   (general equations only) the Schur reduction did not converge, or a
+ *        coefficient holds a non-finite entry
  * n[b] = 0 is a quick return with info 0.  Nothing crosses the ABI as an
  * exception.
  */
@@ -163,6 +166,42 @@ tla_status tla_strsyl_batched(tla_handle h, int batch, int n_max, const int *n, 
                               const int *ldc, int *info);
 tla_status tla_strlyap_batched(tla_handle h, int batch, int n_max, const int *n, const float *const *L,
                                const int *ldl, float *const *S, const int *lds, int *info);
+
+/* General (non-triangular) Sylvester A X + X B = C and Lyapunov
+ * A X + X A^T = S, the equations whose triangular cores are those of the
+ * paper's Fig. 2 (the Motivation paragraph names solvers for Sylvester-like
+ * equations as the purpose of the triangular kernels).  Bartels-Stewart: the
+ * real Schur forms A^T = Z T_A Z^T and B = W T_B W^T are computed on the GPU
+ * (Householder Hessenberg reduction, implicit single-shift QR), the
+ * right-hand side is transformed to Z^T C W (Z^T S Z), the triangular
+ * equation with L = T_A^T and U = T_B (tla_trsyl_batched /
+ * tla_trlyap_batched, in the precision `prec`, refined to FP64 as there) is
+ * solved in place, and X = Z Y W^T (Z Y Z^T) is written back.
+ *   A[b], B[b]: general n[b] x n[b] coefficients, column-major with leading
+ *   dimensions lda[b], ldb[b]; read in full, never written.
+ *   C[b] (S[b]): right-hand side, column-major with leading dimension ldc[b]
+ *   (lds[b]); overwritten with X.  gelyap reads the lower triangle of S and
+ *   writes the full, exactly symmetric X.
+ *   0 <= n[b] <= n_max <= 64 (n_max above 64: TLA_E_UNSUPPORTED).  All arrays
+ *   (pointer arrays included) are device memory owned by the caller.  The
+ *   handle keeps the Schur factors in a workspace of its own (4 n_max^2
+ *   doubles per instance for gesyl, 2 for gelyap).
+ * The coefficients must have real eigenvalues (the triangular cores are
+ * real): info[b] = -4 reports a complex conjugate pair, -5 a QR iteration
+ * that did not converge or a non-finite coefficient entry; the instance's
+ * right-hand side is then left unchanged.  info[b] = k > 0 reports the first
+ * zero denominator lambda_i(A) + lambda_j(B) of the triangular equation
+ * (Schur ordering, as for tla_trsyl_batched); X is then unspecified.
+ * -1 / -2 as for every call (ld of A, B or C).  stat as for the triangular
+ * call (records of the triangular solve).  Asynchronous on the handle's
+ * stream. */
+tla_status tla_gesyl_batched(tla_handle h, tla_prec prec, int batch, int n_max, const int *n,
+                             const double *const *A, const int *lda, const double *const *B,
+                             const int *ldb, double *const *C, const int *ldc, int *info,
+                             tla_stat *stat);
+tla_status tla_gelyap_batched(tla_handle h, tla_prec prec, int batch, int n_max, const int *n,
+                              const double *const *A, const int *lda, double *const *S,
+                              const int *lds, int *info, tla_stat *stat);
 
 /* Mixed batch of all three operations and uneven n in one persistent launch
  * (captured as a HIP graph and replayed when the same descriptor array, batch

@@ -32,7 +32,7 @@ OPS = {"potrf": POTRF, "trsyl": TRSYL, "trlyap": TRLYAP}
 SYMBOLS = [
     "tla_create", "tla_destroy", "tla_set_stream", "tla_sync",
     "tla_potrf_batched", "tla_trsyl_batched", "tla_trlyap_batched", "tla_ragged_batched", "tla_ragged_batched_noalloc",
-    "tla_potrs_batched", "tla_potri_batched",
+    "tla_potrs_batched", "tla_potri_batched", "tla_gesyl_batched", "tla_gelyap_batched",
     "tla_spotrf_batched", "tla_strsyl_batched", "tla_strlyap_batched", "tla_set_plan", "tla_get_plan", "tla_num_candidates", "tla_candidate", "tla_variant_name",
     "tla_tune", "tla_time_plan", "tla_save_table", "tla_load_table", "tla_set_picker",
     "tla_set_refine", "tla_status_string",
@@ -91,6 +91,8 @@ def lib():
             "tla_potrf_batched": (I, [V, I, I, I, P, P, P, P, P]),
             "tla_trsyl_batched": (I, [V, I, I, I, P, P, P, P, P, P, P, P, P]),
             "tla_trlyap_batched": (I, [V, I, I, I, P, P, P, P, P, P, P]),
+            "tla_gesyl_batched": (I, [V, I, I, I, P, P, P, P, P, P, P, P, P]),
+            "tla_gelyap_batched": (I, [V, I, I, I, P, P, P, P, P, P, P]),
             "tla_ragged_batched": (I, [V, I, I, I, P, P, P]),
             "tla_ragged_batched_noalloc": (I, [V, I, I, I, P, P, P]),
             "tla_potrs_batched": (I, [V, I, I, P, I, P, P, P, P, P, P]),
@@ -189,6 +191,15 @@ class Handle:
         check(lib().tla_trsyl_batched(self.h, _prec(prec), batch, n_max, _ptr(n), _ptr(L), _ptr(ldl),
                                       _ptr(U), _ptr(ldu), _ptr(C), _ptr(ldc), _ptr(info), _ptr(stat)),
               "tla_trsyl_batched")
+
+    def gesyl_batched(self, prec, batch, n_max, n, A, lda, B, ldb, C, ldc, info, stat=None):
+        check(lib().tla_gesyl_batched(self.h, _prec(prec), batch, n_max, _ptr(n), _ptr(A), _ptr(lda),
+                                      _ptr(B), _ptr(ldb), _ptr(C), _ptr(ldc), _ptr(info), _ptr(stat)),
+              "tla_gesyl_batched")
+
+    def gelyap_batched(self, prec, batch, n_max, n, A, lda, S, lds, info, stat=None):
+        check(lib().tla_gelyap_batched(self.h, _prec(prec), batch, n_max, _ptr(n), _ptr(A), _ptr(lda),
+                                       _ptr(S), _ptr(lds), _ptr(info), _ptr(stat)), "tla_gelyap_batched")
 
     def trlyap_batched(self, prec, batch, n_max, n, L, ldl, S, lds, info, stat=None):
         check(lib().tla_trlyap_batched(self.h, _prec(prec), batch, n_max, _ptr(n), _ptr(L), _ptr(ldl),
@@ -451,6 +462,22 @@ def trsyl(h: Handle, L, U, C, prec="f64", ops: Operands | None = None):
 def trlyap(h: Handle, L, S, prec="f64", ops: Operands | None = None):
     ops = ops or Operands(S.shape[1], L, S)
     h.trlyap_batched(prec, ops.batch, ops.n_max, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1],
+                     ops.info, ops.stat)
+    return ops
+
+
+def gesyl(h: Handle, A, B, C, prec="f64", ops: Operands | None = None):
+    """General Sylvester A X + X B = C (real spectra), C overwritten with X."""
+    ops = ops or Operands(C.shape[1], A, B, C)
+    h.gesyl_batched(prec, ops.batch, ops.n_max, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1],
+                    ops.ptrs[2], ops.lds[2], ops.info, ops.stat)
+    return ops
+
+
+def gelyap(h: Handle, A, S, prec="f64", ops: Operands | None = None):
+    """General Lyapunov A X + X A^T = S (lower triangle of S read), S overwritten with X."""
+    ops = ops or Operands(S.shape[1], A, S)
+    h.gelyap_batched(prec, ops.batch, ops.n_max, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1],
                      ops.info, ops.stat)
     return ops
 

@@ -44,6 +44,8 @@ struct tla_ctx {
   std::map<long long, bool> exact_choice;         // mode 2: key (op, n, variant, waves) -> measured verdict
   double* work = nullptr;                         // FP64 workspace of the mixed kernels
   size_t work_bytes = 0;
+  double* ge_work = nullptr;                      // general-equation front end: Schur factors, pointer arrays
+  size_t ge_bytes = 0;
   tla_stat* stat_buf = nullptr;                   // refinement records when the caller passes none
   size_t stat_cap = 0;
   // Bumped whenever something a captured ragged graph has baked in changes:

@@ -289,7 +289,9 @@ void tla_ctx::release() {
   tla::ragged_release(this);
   tla::jit_release(this);
   if (work) hipFree(work);
+  if (ge_work) hipFree(ge_work);
   if (stat_buf) hipFree(stat_buf);
   work = nullptr;
+  ge_work = nullptr;
   stat_buf = nullptr;
 }

@@ -57,7 +57,7 @@ def normal(seeds, count):
     return z[:, :count]
 
 
-_OPS = {"potrf": 1, "trsyl": 2, "trlyap": 3, "ragged": 4, "mlp": 5}
+_OPS = {"potrf": 1, "trsyl": 2, "trlyap": 3, "ragged": 4, "mlp": 5, "gesyl": 8, "gelyap": 9}
 
 
 def instance_seeds(tag, op, n, kappa, batch, start=0):
@@ -208,3 +208,37 @@ def ragged_mix(tag, batch, n_lo=3, n_hi=128, fractions=(0.4, 0.3, 0.3)):
     ops = np.minimum(ops, 2)
     ns = (n_lo + np.floor(u[:, 1] * (n_hi - n_lo + 1))).astype(np.int32)
     return ops, np.minimum(ns, n_hi)
+
+
+# ------------------------------------------------ general (non-triangular) coefficients
+def real_spectrum(seeds, n, lo=1.0, hi=2.0, off_scale=None):
+    """M = Q T Q^T: Q Haar orthogonal, T upper triangular with diagonal U[lo, hi]
+    and strictly upper part N(0,1) * off_scale (default 1/n); a non-normal
+    matrix whose eigenvalues are T's diagonal (all real).  The 1/n scale keeps
+    the eigenvalues well conditioned (condition numbers up to about 1e5 at
+    n = 64); at 1/sqrt(n) random triangular matrices grow exponentially
+    ill-conditioned eigenvalues, and close pairs turn into complex pairs
+    once M is rounded to FP64."""
+    if off_scale is None:
+        off_scale = 1.0 / max(n, 1)
+    T = triangular(_sub(seeds, 10), n, lower=False, diag_lo=lo, diag_hi=hi, off_scale=off_scale)
+    Q = haar_orthogonal(_sub(seeds, 11), n)
+    return np.matmul(np.matmul(Q, T), np.swapaxes(Q, 1, 2))
+
+
+def gesyl_problem(tag, n, batch, start=0):
+    """A, B with real spectra in [1, 2] (so every lambda_i(A) + lambda_j(B) >= 2); C ~ N(0,1)."""
+    s = instance_seeds(tag, "gesyl", n, 0.0, batch, start)
+    A = real_spectrum(_sub(s, 0), n)
+    B = real_spectrum(_sub(s, 1), n)
+    C = gaussian(_sub(s, 2), n)
+    return A, B, C
+
+
+def gelyap_problem(tag, n, batch, start=0):
+    """Stable A with real spectrum in [-2, -1]; S symmetric N(0,1)."""
+    s = instance_seeds(tag, "gelyap", n, 0.0, batch, start)
+    A = real_spectrum(_sub(s, 0), n, lo=-2.0, hi=-1.0)
+    S = symmetric(_sub(s, 1), n)
+    return A, S
+
