@@ -173,11 +173,17 @@ int orc_gepp(int m, double *M, double *r) {
       }
       double t = r[k]; r[k] = r[p]; r[p] = t;
     }
+    /* multipliers l_ik = m_ik / m_kk, kept in column k until it is cleared;
+     * then every entry m_ij (i, j > k) receives its one update of step k,
+     * walked down the columns (storage order) */
+    for (int i = k + 1; i < m; ++i) E(M, m, i, k) /= E(M, m, k, k);
+    for (int j = k + 1; j < m; ++j) {
+      const double mkj = E(M, m, k, j);
+      for (int i = k + 1; i < m; ++i) E(M, m, i, j) -= E(M, m, i, k) * mkj;
+    }
     for (int i = k + 1; i < m; ++i) {
-      double f = E(M, m, i, k) / E(M, m, k, k);
+      r[i] -= E(M, m, i, k) * r[k];
       E(M, m, i, k) = 0.0;
-      for (int j = k + 1; j < m; ++j) E(M, m, i, j) -= f * E(M, m, k, j);
-      r[i] -= f * r[k];
     }
   }
   for (int k = m - 1; k >= 0; --k) {
