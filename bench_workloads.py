@@ -1,5 +1,5 @@
 """The benchmark's secondary workloads (one JSON line each), run with
-python bench.py --workload {potrf16,sweep,ragged,large,planner,potrs,variants,plan,exact}.
+python bench.py --workload {potrf16,sweep,ragged,large,planner,potrs,variants,plan,exact,general}.
 
 potrf16 : FP64 Cholesky, 1024 instances at n = 16, replayed many times inside
           one HIP graph (the batch is too small to fill the GPU by itself).
@@ -17,6 +17,9 @@ variants: best time of each blocked-algorithm variant (over tiles, engines,
           n = 128, 256 above (one in-place plan per variant there).
 exact   : exact-size kernels (compiled at run time for each n) against the
           ahead-of-time kernels of the same plan, FP64, n = 4..128.
+general : general Sylvester and Lyapunov equations through the Schur front
+          end (Schur forms, transforms, triangular solve), FP64 and mixed,
+          n = 16, 32, 64, 8192 instances.
 plan    : one operation (first of --ops) at --n, --batch, --prec with the plan
           given by --plan, timed by the library's own timer (for profiling
           one kernel).
@@ -431,6 +434,73 @@ def exact(a):
                       "rows": rows, "compiled": h.exact_size_stats()[0]}))
 
 
+def general(a):
+    """General Sylvester / Lyapunov through the Schur front end, FP64 and
+    mixed triangular solves, n = 16, 32, 64, 8192 instances each."""
+    import torch
+    import oracle
+    import paper_1906_08613_amd as tla
+    from paper_1906_08613_amd import inputs as I
+    h = tla.Handle(0)
+    batch = a.batch if a.batch else 8192
+    for op in ("gesyl", "gelyap"):
+        for n in (16, 32, 64):
+            if op == "gesyl":
+                A, B, C = I.gesyl_problem("general", n, batch)
+                dev = [tla.to_device_cm(A), tla.to_device_cm(B), tla.to_device_cm(C)]
+            else:
+                A, S = I.gelyap_problem("general", n, batch)
+                dev = [tla.to_device_cm(A), tla.to_device_cm(np.tril(S))]
+            pristine = dev[-1].clone()
+            ops = tla.Operands(n, *dev)
+            for prec in ("f64", "mixed_f32"):
+                def run():
+                    if op == "gesyl":
+                        tla.gesyl(h, dev[0], dev[1], dev[2], prec, ops)
+                    else:
+                        tla.gelyap(h, dev[0], dev[1], prec, ops)
+                ts = []
+                for _ in range(4):
+                    dev[-1].copy_(pristine)
+                    torch.cuda.synchronize()
+                    e0, e1 = _events(torch)
+                    e0.record()
+                    run()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ts.append(e0.elapsed_time(e1) * 1e-3)
+                t = float(np.median(ts[1:]))
+                info = ops.info.cpu().numpy()
+                X = tla.from_device_cm(dev[-1][:64])
+                if op == "gesyl":
+                    eta = float(oracle.eta_gesyl_batch(A[:64], B[:64], C[:64], X).max())
+                else:
+                    eta = float(oracle.eta_gelyap_batch(A[:64], S[:64], X).max())
+                row = {"workload": f"{op} {prec} n={n} x{batch}", "solves_per_s": batch / t, "ms": t * 1e3,
+                       "flagged": int((info != 0).sum()), "eta_max_sample64": eta}
+                if prec == "f64":
+                    # host references on a sample: the oracle (Kronecker system,
+                    # O(n^6)) where it finishes, and SciPy's Schur-based solver
+                    import scipy.linalg as sl
+                    k = 4 if n <= 32 else 1
+                    t0 = time.perf_counter()
+                    if op == "gesyl":
+                        oracle.gesyl_batch(A[:k], B[:k], C[:k])
+                    else:
+                        oracle.gelyap_batch(A[:k], S[:k])
+                    row["cpu_oracle_solves_per_s"] = k / (time.perf_counter() - t0)
+                    k = 64
+                    t0 = time.perf_counter()
+                    for b in range(k):
+                        if op == "gesyl":
+                            sl.solve_sylvester(A[b], B[b], C[b])
+                        else:
+                            sl.solve_continuous_lyapunov(A[b], S[b])
+                    row["cpu_scipy_1thread_solves_per_s"] = k / (time.perf_counter() - t0)
+                print(json.dumps(row), flush=True)
+    h.close()
+
+
 def potrs(a):
     import torch
     import oracle
@@ -515,4 +585,4 @@ def variants(a):
 
 def run(a):
     {"potrf16": potrf16, "sweep": sweep, "ragged": ragged, "large": large, "planner": planner,
-     "potrs": potrs, "variants": variants, "plan": plan, "exact": exact}[a.workload](a)
+     "potrs": potrs, "variants": variants, "plan": plan, "exact": exact, "general": general}[a.workload](a)

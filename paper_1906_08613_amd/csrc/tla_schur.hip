@@ -40,7 +40,6 @@
 namespace tla {
 
 constexpr int kSchurMaxN = 64;    // one matrix row / column per lane
-constexpr int kSchurLd = 65;      // LDS leading dimension: odd, so row and column walks spread over the banks
 constexpr int kSchurMaxIts = 60;  // QR iterations without a deflation before the instance is given up
 
 // Per-instance outcomes of the front end (written to info[b]).
@@ -94,45 +93,98 @@ TLA_DI void givens(double x, double y, double& c, double& s) {
   s = ys / r;
 }
 
+// The same rotation without divisions: 1 / sqrt(x^2 + y^2) from the hardware
+// estimate refined by two Newton steps; the scaled form above where
+// x^2 + y^2 could overflow or lose precision to underflow.
+TLA_DI void givens_fast(double x, double y, double& c, double& s) {
+  const double r2 = x * x + y * y;
+  if (!(r2 > 1e-280 && r2 < 1e280)) {
+    givens(x, y, c, s);
+    return;
+  }
+  double ri = __builtin_amdgcn_rsq(r2);
+  ri = __builtin_fma(0.5 * ri, __builtin_fma(-r2 * ri, ri, 1.0), ri);
+  ri = __builtin_fma(0.5 * ri, __builtin_fma(-r2 * ri, ri, 1.0), ri);
+  c = x * ri;
+  s = y * ri;
+}
+
 // Rotation of rows (k, k+1) over columns j0..n-1 and of columns (k, k+1)
-// over rows 0..i1 of H (LDS), as the similarity H <- G^T H G with
-// G = [[c, -s], [s, c]] in the plane (k, k+1).
+// over rows 0..i1 of H (LDS, leading dimension LD), as the similarity
+// H <- G^T H G with G = [[c, -s], [s, c]] in the plane (k, k+1).
+template <int LD>
 TLA_DI void rotate_h(lds_t<double>* H, int n, int k, int j0, int i1, double c, double s) {
   const int l = lane_id();
   if (l >= j0 && l < n) {
-    const double a = H[k + l * kSchurLd], b = H[k + 1 + l * kSchurLd];
-    H[k + l * kSchurLd] = c * a + s * b;
-    H[k + 1 + l * kSchurLd] = c * b - s * a;
+    const double a = H[k + l * LD], b = H[k + 1 + l * LD];
+    H[k + l * LD] = c * a + s * b;
+    H[k + 1 + l * LD] = c * b - s * a;
   }
   compiler_fence();
   if (l <= i1) {
-    const double a = H[l + k * kSchurLd], b = H[l + (k + 1) * kSchurLd];
-    H[l + k * kSchurLd] = c * a + s * b;
-    H[l + (k + 1) * kSchurLd] = c * b - s * a;
+    const double a = H[l + k * LD], b = H[l + (k + 1) * LD];
+    H[l + k * LD] = c * a + s * b;
+    H[l + (k + 1) * LD] = c * b - s * a;
   }
   compiler_fence();
 }
 
-// Q <- Q G for the rotations recorded at positions lo..hi-1 (in that order);
-// lane i holds row i of Q in q[].
-TLA_DI void rotate_q(double (&q)[kSchurMaxN], const lds_t<double>* cs, int lo, int hi) {
+// Q <- Q G for the rotations recorded in cs (pairs (c, s) at 2k, 2k+1) at
+// positions lo..hi-1, in that order; lane i holds row i of Q in q[].  Every
+// unused position holds the identity (1, 0), which leaves q exactly as it
+// is, so the rotations are applied in chunks of 8 whose (c, s) are loaded
+// together, and only chunks that meet [lo, hi) are visited.
+template <int NM>
+TLA_DI void rotate_q(double (&q)[NM], const lds_t<double>* cs, int lo, int hi) {
+  constexpr int CH = 8;
 #pragma unroll
-  for (int k = 0; k + 1 < kSchurMaxN; ++k) {
-    if (k >= lo && k < hi) {
-      const double c = cs[k], s = cs[kSchurMaxN + k];
-      const double a = q[k], b = q[k + 1];
-      q[k] = c * a + s * b;
-      q[k + 1] = c * b - s * a;
+  for (int k0 = 0; k0 + 1 < NM; k0 += CH) {
+    if (k0 + CH > lo && k0 < hi) {
+      double c[CH], s[CH];
+#pragma unroll
+      for (int e = 0; e < CH; ++e) {
+        if (k0 + e + 1 < NM) {
+          c[e] = cs[2 * (k0 + e)];
+          s[e] = cs[2 * (k0 + e) + 1];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < CH; ++e) {
+        const int k = k0 + e;
+        if (k + 1 < NM) {
+          const double a = q[k], b = q[k + 1];
+          q[k] = c[e] * a + s[e] * b;
+          q[k + 1] = c[e] * b - s[e] * a;
+        }
+      }
     }
+    compiler_fence();  // one chunk's (c, s) in registers at a time
   }
+}
+
+// identity rotations back at positions lo..hi-1
+TLA_DI void reset_rotations(lds_t<double>* cs, int lo, int hi) {
+  const int l = lane_id();
+  if (l >= lo && l < hi) {
+    cs[2 * l] = 1.0;
+    cs[2 * l + 1] = 0.0;
+  }
+  compiler_fence();
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_schur(SchurArgs g) {
-  __shared__ double Hs[kSchurMaxN * kSchurLd];
-  __shared__ double cs_s[2 * kSchurMaxN];
+// NM: largest order handled (16, 32 or 64): the LDS holds H (NM x (NM + 1)),
+// each lane holds one row of Q (NM registers).
+template <int NM>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM == 64 ? 1 : (NM == 32 ? 2 : 3)))) void
+k_schur(SchurArgs g) {
+  constexpr int LD = NM + 1;  // odd: row and column walks spread over the banks
+  __shared__ double Hs[NM * LD];
+  __shared__ double vs_s[64];
+  __shared__ double cs_s[2 * NM];
   lds_t<double>* H = to_lds(Hs);
+  lds_t<double>* vs = to_lds(vs_s);
   lds_t<double>* cs = to_lds(cs_s);
   const int si = blockIdx.x / g.batch, b = blockIdx.x - si * g.batch;
   const SchurSet S = g.set[si];
@@ -158,54 +210,58 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_
     if (l < n) {
       const double v = M[l + (size_t)j * ldm];
       finite = finite && __builtin_isfinite(v);
-      if (S.trans) H[j + l * kSchurLd] = v;
-      else H[l + j * kSchurLd] = v;
+      if (S.trans) H[j + l * LD] = v;
+      else H[l + j * LD] = v;
     }
   }
   if (__any(!finite)) {
     if (l == 0) S.status[b] = kGeNoConv;
     return;
   }
+  if (l < NM) {
+    cs[2 * l] = 1.0;
+    cs[2 * l + 1] = 0.0;
+  }
   compiler_fence();
 
-  double q[kSchurMaxN];
+  double q[NM];
 #pragma unroll
-  for (int j = 0; j < kSchurMaxN; ++j) q[j] = l == j ? 1.0 : 0.0;
+  for (int j = 0; j < NM; ++j) q[j] = l == j ? 1.0 : 0.0;
 
   // ---- Householder reduction to upper Hessenberg form: H <- P H P, Q <- Q P,
   // P = I - tau v v^T zeroing column k below the subdiagonal (v_{k+1} = 1)
   for (int k = 0; k + 2 < n; ++k) {
-    const double xi = (l > k && l < n) ? H[l + k * kSchurLd] : 0.0;
+    const double xi = (l > k && l < n) ? H[l + k * LD] : 0.0;
     const double ss = wave_sum(l > k + 1 ? xi * xi : 0.0);
     if (ss == 0.0) continue;
     const double alpha = read_lane(xi, k + 1);
     const double beta = -copysign(sqrt(alpha * alpha + ss), alpha);
     const double tau = (beta - alpha) / beta;
     const double sc = 1.0 / (alpha - beta);
-    cs[l] = l == k + 1 ? 1.0 : (l > k + 1 ? xi * sc : 0.0);
+    vs[l] = l == k + 1 ? 1.0 : (l > k + 1 ? xi * sc : 0.0);
     compiler_fence();
     // left: rows k+1..n-1 of columns k+1..n-1 (lane = column)
     if (l > k && l < n) {
       double w = 0.0;
-      for (int i = k + 1; i < n; ++i) w += cs[i] * H[i + l * kSchurLd];
+      for (int i = k + 1; i < n; ++i) w += vs[i] * H[i + l * LD];
       w *= tau;
-      for (int i = k + 1; i < n; ++i) H[i + l * kSchurLd] -= cs[i] * w;
-      H[l + k * kSchurLd] = l == k + 1 ? beta : 0.0;
+      for (int i = k + 1; i < n; ++i) H[i + l * LD] -= vs[i] * w;
+      H[l + k * LD] = l == k + 1 ? beta : 0.0;
     }
     compiler_fence();
     // right: columns k+1..n-1 of every row (lane = row)
     if (l < n) {
       double u = 0.0;
-      for (int j = k + 1; j < n; ++j) u += H[l + j * kSchurLd] * cs[j];
+      for (int j = k + 1; j < n; ++j) u += H[l + j * LD] * vs[j];
       u *= tau;
-      for (int j = k + 1; j < n; ++j) H[l + j * kSchurLd] -= u * cs[j];
+      for (int j = k + 1; j < n; ++j) H[l + j * LD] -= u * vs[j];
     }
     double u = 0.0;
 #pragma unroll
-    for (int j = 0; j < kSchurMaxN; ++j) u += q[j] * cs[j];
+    for (int j = 0; j < NM; ++j) u += q[j] * vs[j];
     u *= tau;
 #pragma unroll
-    for (int j = 0; j < kSchurMaxN; ++j) q[j] -= u * cs[j];
+    for (int j = 0; j < NM; ++j) q[j] -= u * vs[j];
     compiler_fence();
   }
 
@@ -218,18 +274,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_
     // diagonal neighbours
     bool neg = false;
     if (l >= 1 && l <= hi) {
-      const double sub = fabs(H[l + (l - 1) * kSchurLd]);
-      double tst = fabs(H[(l - 1) + (l - 1) * kSchurLd]) + fabs(H[l + l * kSchurLd]);
+      const double sub = fabs(H[l + (l - 1) * LD]);
+      double tst = fabs(H[(l - 1) + (l - 1) * LD]) + fabs(H[l + l * LD]);
       if (tst == 0.0) {
-        if (l >= 2) tst += fabs(H[(l - 1) + (l - 2) * kSchurLd]);
-        if (l + 1 <= hi) tst += fabs(H[(l + 1) + l * kSchurLd]);
+        if (l >= 2) tst += fabs(H[(l - 1) + (l - 2) * LD]);
+        if (l + 1 <= hi) tst += fabs(H[(l + 1) + l * LD]);
       }
       neg = sub <= smlnum || sub <= ulp * tst;
     }
     const unsigned long long mask = __ballot(neg);
     const int lo = mask ? 63 - __clzll(mask) : 0;
     compiler_fence();
-    if (lo > 0 && l == 0) H[lo + (lo - 1) * kSchurLd] = 0.0;
+    if (lo > 0 && l == 0) H[lo + (lo - 1) * LD] = 0.0;
     compiler_fence();
     if (lo == hi) {  // 1 x 1 block: an eigenvalue
       hi -= 1;
@@ -237,8 +293,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_
       continue;
     }
     if (lo == hi - 1) {  // 2 x 2 block: split it if its eigenvalues are real
-      const double a = uni(H[lo + lo * kSchurLd]), bq = uni(H[lo + hi * kSchurLd]);
-      const double e = uni(H[hi + lo * kSchurLd]), d = uni(H[hi + hi * kSchurLd]);
+      const double a = uni(H[lo + lo * LD]), bq = uni(H[lo + hi * LD]);
+      const double e = uni(H[hi + lo * LD]), d = uni(H[hi + hi * LD]);
       const double p = 0.5 * (a - d), disc = p * p + bq * e;
       if (disc < 0.0) {
         fail = kGeComplex;
@@ -251,14 +307,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_
         double c, s;
         givens(z, e, c, s);
         compiler_fence();
-        rotate_h(H, n, lo, lo, hi, c, s);
+        rotate_h<LD>(H, n, lo, lo, hi, c, s);
         if (l == 0) {
-          cs[lo] = c;
-          cs[kSchurMaxN + lo] = s;
-          H[hi + lo * kSchurLd] = 0.0;
+          cs[2 * lo] = c;
+          cs[2 * lo + 1] = s;
+          H[hi + lo * LD] = 0.0;
         }
         compiler_fence();
-        rotate_q(q, cs, lo, lo + 1);
+        rotate_q<NM>(q, cs, lo, lo + 1);
+        compiler_fence();
+        reset_rotations(cs, lo, lo + 1);
       }
       hi -= 2;
       its = 0;
@@ -266,8 +324,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_
     }
     if (++its > kSchurMaxIts) {
       // no deflation: a complex pair at the bottom of the window, or no convergence
-      const double a = uni(H[(hi - 1) + (hi - 1) * kSchurLd]), bq = uni(H[(hi - 1) + hi * kSchurLd]);
-      const double e = uni(H[hi + (hi - 1) * kSchurLd]), d = uni(H[hi + hi * kSchurLd]);
+      const double a = uni(H[(hi - 1) + (hi - 1) * LD]), bq = uni(H[(hi - 1) + hi * LD]);
+      const double e = uni(H[hi + (hi - 1) * LD]), d = uni(H[hi + hi * LD]);
       const double p = 0.5 * (a - d);
       fail = p * p + bq * e < 0.0 ? kGeComplex : kGeNoConv;
       break;
@@ -275,8 +333,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_
     // shift: the eigenvalue of the trailing 2 x 2 block nearer its last
     // diagonal entry (Wilkinson), its last diagonal entry when that block has
     // complex eigenvalues, and an ad hoc exceptional shift every 10th step
-    const double a = uni(H[(hi - 1) + (hi - 1) * kSchurLd]), bq = uni(H[(hi - 1) + hi * kSchurLd]);
-    const double e = uni(H[hi + (hi - 1) * kSchurLd]), d = uni(H[hi + hi * kSchurLd]);
+    const double a = uni(H[(hi - 1) + (hi - 1) * LD]), bq = uni(H[(hi - 1) + hi * LD]);
+    const double e = uni(H[hi + (hi - 1) * LD]), d = uni(H[hi + hi * LD]);
     double sigma;
     if (its % 10 == 0) {
       sigma = d + 0.75 * fabs(e);
@@ -289,27 +347,59 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_
       }
     }
     // the sweep: the first rotation from the shifted first column, then the
-    // bulge chased down the window
-    double x = uni(H[lo + lo * kSchurLd]) - sigma, y = uni(H[(lo + 1) + lo * kSchurLd]);
+    // bulge chased down the window.  Rotation k updates rows (k, k+1) (lane =
+    // column) and then columns (k, k+1) (lane = row).  Both operand pairs are
+    // read before either update: the row update changes no column operand
+    // except those of rows k and k+1, which lanes k and k+1 take from the row
+    // update's results (cross-lane reads), and the next rotation's pair
+    // (h_{k+1,k}, h_{k+2,k}) comes from the column update's results the same
+    // way; the LDS then carries only the stores, and the loads of the next
+    // rotation overlap the computation of its (c, s).
+    double x = uni(H[lo + lo * LD]) - sigma, y = uni(H[(lo + 1) + lo * LD]);
+    compiler_fence();
     for (int k = lo; k < hi; ++k) {
-      if (k > lo) {
-        x = uni(H[k + (k - 1) * kSchurLd]);
-        y = uni(H[(k + 1) + (k - 1) * kSchurLd]);
-      }
-      double c, s;
-      givens(x, y, c, s);
       const int j0 = k > lo ? k - 1 : lo;
       const int i1 = k + 2 < hi ? k + 2 : hi;
-      rotate_h(H, n, k, j0, i1, c, s);
+      const bool rl = l >= j0 && l < n, cl = l <= i1;
+      const int lr = l < n ? l : n - 1;
+      const double ra = H[k + lr * LD], rb = H[(k + 1) + lr * LD];
+      double ca = H[lr + k * LD], cb = H[lr + (k + 1) * LD];
+      double c, s;
+      givens_fast(x, y, c, s);
+      const double ra2 = c * ra + s * rb;
+      double rb2 = c * rb - s * ra;
+      if (k > lo && l == k - 1) rb2 = 0.0;  // the annihilated bulge
+      if (rl) {
+        H[k + l * LD] = ra2;
+        H[(k + 1) + l * LD] = rb2;
+      }
+      const double h00 = read_lane(ra2, k), h01 = read_lane(ra2, k + 1);
+      const double h10 = read_lane(rb2, k), h11 = read_lane(rb2, k + 1);
+      if (l == k) {
+        ca = h00;
+        cb = h01;
+      } else if (l == k + 1) {
+        ca = h10;
+        cb = h11;
+      }
+      const double ca2 = c * ca + s * cb, cb2 = c * cb - s * ca;
+      if (cl) {
+        H[l + k * LD] = ca2;
+        H[l + (k + 1) * LD] = cb2;
+      }
       if (l == 0) {
-        if (k > lo) H[(k + 1) + (k - 1) * kSchurLd] = 0.0;  // the annihilated bulge
-        cs[k] = c;
-        cs[kSchurMaxN + k] = s;
+        cs[2 * k] = c;
+        cs[2 * k + 1] = s;
+      }
+      if (k + 1 < hi) {
+        x = read_lane(ca2, k + 1);
+        y = read_lane(ca2, k + 2);
       }
       compiler_fence();
     }
-    rotate_q(q, cs, lo, hi);
+    rotate_q<NM>(q, cs, lo, hi);
     compiler_fence();
+    reset_rotations(cs, lo, hi);
   }
   if (fail != 0) {
     if (l == 0) S.status[b] = fail;
@@ -322,13 +412,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_
   for (int j = 0; j < n; ++j) {
     if (l < n) {
       double v;
-      if (S.lower) v = l >= j ? H[j + l * kSchurLd] : 0.0;
-      else v = l <= j ? H[l + j * kSchurLd] : 0.0;
+      if (S.lower) v = l >= j ? H[j + l * LD] : 0.0;
+      else v = l <= j ? H[l + j * LD] : 0.0;
       T[l + (size_t)j * ld] = v;
     }
   }
 #pragma unroll
-  for (int j = 0; j < kSchurMaxN; ++j)
+  for (int j = 0; j < NM; ++j)
     if (j < n && l < n) Q[l + (size_t)j * ld] = q[j];
   if (l == 0) S.status[b] = 0;
 }
@@ -546,7 +636,10 @@ tla_status ge_solve(tla_ctx* h, int op, tla_prec prec, int batch, int n_max, con
   sa.stride = Lo.stride;
   sa.set[0] = SchurSet{A, lda, 1, 1, Lt, Zq, st0};
   if (syl) sa.set[1] = SchurSet{B, ldb, 0, 0, Ut, Wq, st1};
-  hipLaunchKernelGGL(k_schur, dim3(batch * sa.nsets), dim3(64), 0, h->stream, sa);
+  const dim3 sg(batch * sa.nsets);
+  if (nm <= 16) hipLaunchKernelGGL(k_schur<16>, sg, dim3(64), 0, h->stream, sa);
+  else if (nm <= 32) hipLaunchKernelGGL(k_schur<32>, sg, dim3(64), 0, h->stream, sa);
+  else hipLaunchKernelGGL(k_schur<64>, sg, dim3(64), 0, h->stream, sa);
   GE_HIP(hipGetLastError());
 
   PrepArgs pa{};

@@ -222,6 +222,13 @@ def real_spectrum(seeds, n, lo=1.0, hi=2.0, off_scale=None):
     if off_scale is None:
         off_scale = 1.0 / max(n, 1)
     T = triangular(_sub(seeds, 10), n, lower=False, diag_lo=lo, diag_hi=hi, off_scale=off_scale)
+    # stratified eigenvalues: one in each of n equal slots of [lo, hi] (kept
+    # off the slot edges), in random order, so that no two are closer than
+    # (hi - lo) / (2 n); independent uniform draws put close pairs into a few
+    # instances per thousand, which rounding turns into complex pairs
+    u = uniform(_sub(seeds, 12), 2 * n).reshape(len(seeds), 2, n)
+    slot = np.argsort(u[:, 0, :], axis=1)
+    T[:, np.arange(n), np.arange(n)] = lo + (hi - lo) * (slot + 0.25 + 0.5 * u[:, 1, :]) / max(n, 1)
     Q = haar_orthogonal(_sub(seeds, 11), n)
     return np.matmul(np.matmul(Q, T), np.swapaxes(Q, 1, 2))
 
