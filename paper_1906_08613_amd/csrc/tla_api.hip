@@ -369,6 +369,9 @@ tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& 
     // the work matrices in the workspace faulted the GPU on their first
     // Lyapunov run, cause not found; the code path is switched off.)
     if (prec != TLA_F64) return TLA_E_UNSUPPORTED;
+    // left-looking Cholesky: block panels, each update one batched product
+    // (from n = 384; at n = 256 the one-workgroup kernel measured faster)
+    if (op == TLA_POTRF && p.variant == 1 && a.n_max >= 384) return potrf_panel(h, a);
     a.ntmax = (a.n_max + 15) / 16;
     KFn fn64 = large_kernel(op, p.variant);
     if (!fn64) return TLA_E_UNSUPPORTED;

@@ -46,6 +46,8 @@ struct tla_ctx {
   size_t work_bytes = 0;
   double* ge_work = nullptr;                      // general-equation front end: Schur factors, pointer arrays
   size_t ge_bytes = 0;
+  void* panel_work = nullptr;                     // large Cholesky by block panels: per-instance arrays
+  size_t panel_bytes = 0;
   tla_stat* stat_buf = nullptr;                   // refinement records when the caller passes none
   size_t stat_cap = 0;
   // Bumped whenever something a captured ragged graph has baked in changes:
@@ -84,6 +86,8 @@ tla_status exact_size_decide(tla_ctx* h, int op, int n, int batch, const tla_pla
 // Per-device set-up of the allocation-free ragged path (tla_ragged.hip).
 tla_status noalloc_init(int device);
 tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& a);
+// Large FP64 Cholesky, left-looking by block panels (tla_panel.hip).
+tla_status potrf_panel(tla_ctx* h, const KArgs& a);
 size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int placement);
 int choose_placement(tla_ctx* h, int op, int prec, const tla_plan& p, int ntmax, size_t* lds);
 bool plan_valid(int op, const tla_plan& p);

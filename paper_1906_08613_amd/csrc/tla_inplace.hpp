@@ -47,6 +47,23 @@ struct IOView {
     coords(i, j, r, c);
     if (r < n && c < n && !(upper_only && r > c)) to_gbl(p)[r + (size_t)c * ld] = S(v);
   }
+  // the 16 x 16 block at (r0, c0) lies inside n x n and strictly above the
+  // diagonal where only the upper triangle is read, so raw() may read it
+  // without clamping or selects.  Used by the Cholesky products (both
+  // operands are views of the factor); for the symmetric Lyapunov view the
+  // unmasked path measured slower and stays compiled out.
+  TLA_DI bool interior16() const {
+    if constexpr (SYM) return false;
+    const int rhi = r0 + 15, chi = c0 + 15;
+    if (rhi >= n || chi >= n) return false;
+    if (upper_only && rhi > c0) return false;
+    return true;
+  }
+  TLA_DI T raw(int i, int j) const {
+    int r, c;
+    coords(i, j, r, c);
+    return T(to_gbl(p)[r + (size_t)c * ld]);
+  }
   TLA_DI void fence() const { __threadfence_block(); }
   static constexpr bool mirrors() { return SYM; }
   TLA_DI IOView sub(int i0, int j0) const {

@@ -1,0 +1,361 @@
+// Left-looking Cholesky of the large sizes by block panels, as a sequence of
+// launches that each cover the whole batch.  For the panel of rows
+// [k0, k0 + NB) of the upper factor (the partitioned form of the paper's
+// Cholesky, Fig. 2a, taken by block rows):
+//
+//   A(k0:k0+NB, k0:n) -= X(0:k0, k0:k0+NB)^T X(0:k0, k0:n)    panel update
+//   X(k0:k0+NB, k0:k0+NB) = chol(A(k0:k0+NB, k0:k0+NB))         diagonal block
+//   X(k0:k0+NB, k0+NB:n) = X_kk^{-T} A(k0:k0+NB, k0+NB:n)       panel solve
+//
+// The update carries almost all of the n^3/3 flops.  It runs as one batched
+// product over all instances (k_bgemm_chol: 64 x 64 output blocks per
+// workgroup, 16-deep operand panels staged in LDS, FP64 matrix cores),
+// instead of tile products inside one workgroup per instance: a 16-wave
+// instance workgroup re-reads every operand tile from memory and keeps one
+// compute unit busy per instance.  The diagonal block uses the in-place
+// Cholesky kernel (order NB, four waves) on pointers into the caller's
+// matrices, and the panel solve runs many 16-column tiles per instance side
+// by side (k_panel_trsm).
+// Only the upper triangle is read or written.
+#include <cstdio>
+#include <cstdlib>
+
+#include "tla_inplace.hpp"
+#include "tla_host.h"
+
+namespace tla {
+
+constexpr int kPanelNB = 128;  // panel height
+
+namespace {
+
+#define PN_HIP(x)                                                                   \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) {                                                         \
+      if (getenv("TLA_LOG")) fprintf(stderr, "tla: %s failed: %s\n", #x, hipGetErrorString(e_)); \
+      return TLA_E_HIP;                                                             \
+    }                                                                               \
+  } while (0)
+
+struct PanelArgs {
+  int batch, n_max, k0, nb;
+  const int* n;          // the instance's order, 0 when it is invalid or has failed validation
+  double* const* x;      // the caller's matrices
+  const int* ld;
+};
+
+// C(i, j) -= sum_k X(k, k0 + i) X(k, k0 + j) over k < k0, for
+// 0 <= i < min(nb, n - k0), i <= j < n - k0 (upper triangle only).
+// Grid (column blocks of 64, row blocks of 64, instances), 4 waves; wave w
+// computes the 32 x 32 quadrant (w >> 1, w & 1) of the block as 2 x 2 tiles.
+constexpr int kBg = 64, kBk = 16, kBld = kBg + 4;
+
+__global__ __launch_bounds__(256) void k_bgemm_chol(PanelArgs g) {
+  __shared__ double sA[kBk * kBld];
+  __shared__ double sB[kBk * kBld];
+  const int b = blockIdx.z;
+  const int n = g.n[b];
+  const int k0 = g.k0;
+  if (n <= k0) return;
+  const int M = n - k0 < g.nb ? n - k0 : g.nb, N = n - k0;
+  const int i0 = blockIdx.y * kBg, j0 = blockIdx.x * kBg;
+  if (i0 >= M || j0 >= N || i0 > j0 + kBg - 1) return;  // nothing of the upper triangle here
+  const int ld = g.ld[b];
+  const gbl_t<double>* X = to_gbl(static_cast<const double*>(g.x[b]));
+  const int t = threadIdx.x, l = lane_id(), w = wave_id();
+  // this thread's four elements of each 16 x 64 operand panel: k = e & 15,
+  // column e >> 4 (16 consecutive k of one column per 16 lanes: 128 B)
+  const gbl_t<double>* pa[4];
+  const gbl_t<double>* pb[4];
+  bool ma[4], mb[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = t + 256 * r, kk = e & 15, c = e >> 4;
+    const int ia = i0 + c < M ? i0 + c : M - 1, jb = j0 + c < N ? j0 + c : N - 1;
+    ma[r] = i0 + c < M;
+    mb[r] = j0 + c < N;
+    pa[r] = X + kk + (size_t)(k0 + ia) * ld;
+    pb[r] = X + kk + (size_t)(k0 + jb) * ld;
+  }
+  double ra[4], rb[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    ra[r] = ma[r] ? pa[r][0] : 0.0;
+    rb[r] = mb[r] ? pb[r][0] : 0.0;
+  }
+  typedef double d4v __attribute__((ext_vector_type(4)));
+  d4v acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = d4v{0.0, 0.0, 0.0, 0.0};
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32, i16 = l & 15, kq = l >> 4;
+  for (int kt = 0; kt < k0; kt += kBk) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = t + 256 * r, kk = e & 15, c = e >> 4;
+      sA[kk * kBld + c] = ra[r];
+      sB[kk * kBld + c] = rb[r];
+    }
+    __syncthreads();
+    if (kt + kBk < k0) {  // the next panel's loads overlap this panel's products
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        ra[r] = ma[r] ? pa[r][kt + kBk] : 0.0;
+        rb[r] = mb[r] ? pb[r][kt + kBk] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) {
+      const int kr = (4 * k4 + kq) * kBld;
+      double fa[2], fb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) fa[a] = sA[kr + wr + 16 * a + i16];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) fb[c] = sB[kr + wc + 16 * c + i16];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
+    }
+  }
+  gbl_t<double>* C = to_gbl(g.x[b]);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr + 16 * a + kq + 4 * r, j = j0 + wc + 16 * c + i16;
+        if (i < M && j < N && i <= j) {
+          gbl_t<double>* p = C + (k0 + i) + (size_t)(k0 + j) * ld;
+          *p = *p - acc[a][c][r];
+        }
+      }
+}
+
+struct PrepArgs {
+  int batch, n_max, k0, nb;
+  const int* n_in;       // the caller's orders
+  const int* ld;
+  double* const* x;
+  int* n_use;            // order in use: the caller's, 0 once invalid
+  int* n_blk;            // diagonal block order at this panel
+  int* m_rhs;            // columns right of the diagonal block
+  double** diag;         // diagonal block
+  double** panel;        // block right of it
+  int* info;             // the caller's info (validation at the first panel)
+  tla_stat* stat;
+};
+
+__global__ void k_panel_prep(PrepArgs g) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= g.batch) return;
+  int n;
+  if (g.k0 == 0) {
+    n = g.n_in[b];
+    int st = 0;
+    if (n < 0 || n > g.n_max) st = -1;
+    else if (g.ld[b] < (n > 1 ? n : 1)) st = -2;
+    g.info[b] = st;
+    if (st != 0) n = 0;
+    g.n_use[b] = n;
+    if (g.stat) {
+      g.stat[b].iters = 0;
+      g.stat[b].flags = 0;
+      g.stat[b].eta = 0.0;
+    }
+  } else {
+    n = g.n_use[b];
+  }
+  const int rem = n - g.k0;
+  const int nb = rem <= 0 ? 0 : (rem < g.nb ? rem : g.nb);
+  g.n_blk[b] = nb;
+  g.m_rhs[b] = rem > g.nb ? rem - g.nb : 0;
+  const int ld = g.ld[b];
+  double* x = g.x[b];
+  // pointers stay inside the matrix where nothing is left to do
+  const int k = nb > 0 ? g.k0 : 0;
+  g.diag[b] = x + k + (size_t)k * ld;
+  g.panel[b] = x + k + (size_t)(nb > 0 && rem > g.nb ? g.k0 + g.nb : k) * ld;
+}
+
+// The first failing pivot of this panel's diagonal block, as a leading minor
+// of the whole matrix; later panels of a failed instance are skipped.
+__global__ void k_panel_merge(int batch, int k0, const int* blk_info, int* info, int* n_use) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const int s = blk_info[b];
+  if (info[b] == 0 && s > 0) {
+    info[b] = k0 + s;
+    n_use[b] = 0;
+  }
+}
+
+// Panel solve B := X_kk^{-T} B, B the block right of the diagonal block.
+// One workgroup of 12 waves per (instance, 12 column tiles of B): the
+// block's upper triangle is staged in LDS once (zero below the diagonal, one
+// on the padded diagonal), and each wave solves one 16-column tile of B held
+// in registers, tile row by tile row.  The FP64 accumulator layout of the
+// matrix cores (lane l: column l & 15, rows (l >> 4) + 4r) is also the layout
+// of their B operand for the four k-steps of a 16-deep product, so the solved
+// tiles feed the products X_KI^T Z_K directly from registers.
+// 12 waves: three per SIMD leave each wave the registers for its eight
+// solution tiles (16 waves spilled); scratch: the strip solver's 16 x 17 tile
+constexpr int kTsNW = 12, kTsNT = kPanelNB / 16, kTsLd = 17, kTsTile = 16 * kTsLd, kTsScr = kTsTile;
+
+struct SolveArgs {
+  const int* n_blk;
+  const int* m_rhs;
+  const int* ld;
+  double* const* diag;
+  double* const* panel;
+};
+
+TLA_DI int tri_index(int k, int i) { return i * (i + 1) / 2 + k; }  // upper tile (k, i), k <= i
+
+__global__ __launch_bounds__(kTsNW * 64) void k_panel_trsm(SolveArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x;
+  const int n = g.n_blk[b], m = g.m_rhs[b];
+  if (n <= 0 || m <= 0 || blockIdx.y * kTsNW * 16 >= m) return;
+  const int ld = g.ld[b];
+  const gbl_t<double>* X = to_gbl(static_cast<const double*>(g.diag[b]));
+  lds_t<double>* S = to_lds(reinterpret_cast<double*>(smem));
+  lds_t<double>* wbuf = S + kTsNT * (kTsNT + 1) / 2 * kTsTile + wave_id() * kTsScr;
+  const int nt = (n + 15) / 16;
+  // stage the upper tiles, column-major inside each tile (coalesced along rows)
+  const int ntile = nt * (nt + 1) / 2;
+  for (int q = threadIdx.x; q < ntile * 256; q += blockDim.x) {
+    const int tix = q >> 8, e = q & 255, r = e & 15, c = e >> 4;
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= tix) ++i;
+    const int k = tix - i * (i + 1) / 2;
+    const int row = 16 * k + r, col = 16 * i + c;
+    const int rr = row < n ? row : n - 1, cc = col < n ? col : n - 1;
+    const double raw = X[rr + (size_t)cc * ld];
+    double v;
+    if (row < n && col < n) v = row <= col ? raw : 0.0;
+    else v = row == col ? 1.0 : 0.0;
+    S[tix * kTsTile + r + c * kTsLd] = v;
+  }
+  __syncthreads();
+  const int J = blockIdx.y * kTsNW + wave_id();
+  if (16 * J >= m) return;
+  const int l = lane_id(), jc = 16 * J + (l & 15), kq = l >> 4;
+  gbl_t<double>* B = to_gbl(g.panel[b]);
+  const bool cin = jc < m;
+  const int jcc = cin ? jc : m - 1;
+  Tile<double, 16> Z[kTsNT];
+#pragma unroll
+  for (int I = 0; I < kTsNT; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * I + kq + 4 * r;
+      const int rr = row < n ? row : n - 1;
+      const double raw = B[rr + (size_t)jcc * ld];
+      Z[I].v[r] = (row < n && cin) ? raw : 0.0;
+    }
+#pragma unroll
+  for (int I = 0; I < kTsNT; ++I) {
+    if (I >= nt) break;
+    d4 acc = {Z[I].v[0], Z[I].v[1], Z[I].v[2], Z[I].v[3]};
+#pragma unroll
+    for (int K = 0; K < I; ++K) {
+      const lds_t<double>* T = S + tri_index(K, I) * kTsTile;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-T[(4 * kk + kq) + (l & 15) * kTsLd], Z[K].v[kk], acc, 0, 0, 0);
+    }
+    Tile<double, 16> c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c.v[r] = acc[r];
+    tile_trsm_ut<double, 16>(c, View<double, true>{S + tri_index(I, I) * kTsTile, 1, kTsLd}, wbuf);
+    Z[I] = c;
+  }
+#pragma unroll
+  for (int I = 0; I < kTsNT; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * I + kq + 4 * r;
+      if (row < n && cin) B[row + (size_t)jc * ld] = Z[I].v[r];
+    }
+}
+
+size_t panel_trsm_lds() { return ((size_t)kTsNT * (kTsNT + 1) / 2 * kTsTile + (size_t)kTsNW * kTsScr) * sizeof(double); }
+
+}  // namespace
+
+// Large FP64 Cholesky by block panels; a as for the in-place kernels.
+tla_status potrf_panel(tla_ctx* h, const KArgs& a) {
+  const int batch = a.batch;
+  // workspace: four int arrays and two pointer arrays
+  const size_t ints = (size_t)4 * batch * sizeof(int);
+  const size_t ptr_off = (ints + 255) & ~(size_t)255;
+  const size_t bytes = ptr_off + (size_t)2 * batch * sizeof(double*);
+  if (bytes > h->panel_bytes) {
+    if (h->panel_work) {
+      PN_HIP(hipStreamSynchronize(h->stream));
+      hipFree(h->panel_work);
+      h->panel_work = nullptr;
+      h->panel_bytes = 0;
+    }
+    if (hipMalloc(&h->panel_work, bytes) != hipSuccess) return TLA_E_NOMEM;
+    h->panel_bytes = bytes;
+  }
+  char* base = reinterpret_cast<char*>(h->panel_work);
+  int* n_use = reinterpret_cast<int*>(base);
+  int* n_blk = n_use + batch;
+  int* m_rhs = n_use + 2 * batch;
+  int* blk_info = n_use + 3 * batch;
+  double** diag = reinterpret_cast<double**>(base + ptr_off);
+  double** panel = reinterpret_cast<double**>(diag + batch);
+
+  const int nb = kPanelNB;
+  // diagonal blocks: in place, four waves per block (the batch is small
+  // next to the number of compute units)
+  tla_plan pd = default_plan(TLA_POTRF, nb, TLA_F64);
+  pd.variant = 1;  // left-looking: a block row's tiles go to all four waves
+  pd.waves = 4;
+  const dim3 pg((batch + 255) / 256), pb(256);
+  for (int k0 = 0; k0 < a.n_max; k0 += nb) {
+    if (k0 > 0) {
+      PanelArgs ga{batch, a.n_max, k0, nb, n_use, a.c, a.ldc};
+      const dim3 grid((a.n_max - k0 + kBg - 1) / kBg, (nb + kBg - 1) / kBg, batch);
+      hipLaunchKernelGGL(k_bgemm_chol, grid, dim3(256), 0, h->stream, ga);
+      PN_HIP(hipGetLastError());
+    }
+    PrepArgs pa{batch, a.n_max, k0, nb, a.n, a.ldc, a.c, n_use, n_blk, m_rhs, diag, panel, a.info, a.stat};
+    hipLaunchKernelGGL(k_panel_prep, pg, pb, 0, h->stream, pa);
+    PN_HIP(hipGetLastError());
+    // diagonal block
+    KArgs kd{};
+    kd.batch = batch;
+    kd.n_max = nb;
+    kd.n = n_blk;
+    kd.c = diag;
+    kd.ldc = a.ldc;
+    kd.info = blk_info;
+    tla_status s = launch(h, TLA_POTRF, TLA_F64, pd, kd);
+    if (s != TLA_OK) return s;
+    // panel solve with the block's factor (skipped where the block failed:
+    // its instance is then unspecified, as the caller's contract allows)
+    if (k0 + nb < a.n_max) {
+      SolveArgs sa{n_blk, m_rhs, a.ldc, diag, panel};
+      const size_t lds = panel_trsm_lds();
+      PN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_panel_trsm),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      const int tiles = (a.n_max - k0 - nb + 15) / 16;
+      hipLaunchKernelGGL(k_panel_trsm, dim3(batch, (tiles + kTsNW - 1) / kTsNW), dim3(64 * kTsNW), lds, h->stream,
+                         sa);
+      PN_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_panel_merge, pg, pb, 0, h->stream, batch, k0, blk_info, a.info, n_use);
+    PN_HIP(hipGetLastError());
+  }
+  return TLA_OK;
+}
+
+}  // namespace tla

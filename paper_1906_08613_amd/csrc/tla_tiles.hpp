@@ -155,6 +155,15 @@ TLA_DI void tzero(Tile<T, TB>& c) {
 template <class T, int TB, int ENG>
 struct Gemm;
 
+// Views of global memory that can tell whether a whole 16 x 16 block lies
+// inside the matrix and its referenced part (interior16()) offer raw(i, j),
+// an unmasked load; a product whose two operands are interior reads them that
+// way, and only edge and diagonal blocks pay for the clamping and selects.
+template <class V, class = void>
+struct HasRaw : std::false_type {};
+template <class V>
+struct HasRaw<V, std::void_t<decltype(std::declval<const V&>().interior16())>> : std::true_type {};
+
 // Matrix cores in the working precision (f64 16x16x4 or f32 16x16x4).
 // load() fetches one step's operand fragments, mma() consumes them.
 template <class T>
@@ -163,6 +172,16 @@ struct Gemm<T, 16, ENG_MFMA> {
   template <class VA, class VB>
   static TLA_DI void load(F& f, const VA& A, const VB& B) {
     const int l = lane_id(), i = l & 15, kq = l >> 4;
+    if constexpr (HasRaw<VA>::value && HasRaw<VB>::value) {
+      if (A.interior16() && B.interior16()) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          f.a[kk] = -A.raw(i, 4 * kk + kq);
+          f.b[kk] = B.raw(4 * kk + kq, i);
+        }
+        return;
+      }
+    }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       f.a[kk] = -A(i, 4 * kk + kq);

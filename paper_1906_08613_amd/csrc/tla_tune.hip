@@ -290,6 +290,8 @@ void tla_ctx::release() {
   tla::jit_release(this);
   if (work) hipFree(work);
   if (ge_work) hipFree(ge_work);
+  if (panel_work) hipFree(panel_work);
+  panel_work = nullptr;
   if (stat_buf) hipFree(stat_buf);
   work = nullptr;
   ge_work = nullptr;

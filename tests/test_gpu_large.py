@@ -129,3 +129,48 @@ def test_largest_size_1024_against_oracle(h, orc, op):
     colmax = np.abs(Xr).max(axis=1, keepdims=True)
     assert np.max(np.abs(X - Xr) / np.where(colmax == 0, 1.0, colmax)) <= 1e-12
     assert eta.max() <= 1e-13
+
+
+def test_large_potrf_panels_uneven_n_and_failures(h, orc):
+    # the left-looking large Cholesky runs by block panels of 128 rows: uneven
+    # orders in one batch (below, at and across panel edges), a leading
+    # dimension above n, and instances that fail in the first and in a later
+    # panel, against the oracle; the strict lower triangle stays untouched
+    n_max, ld = 300, 305
+    ns = [300, 0, 129, 257, 140, 128, 300, 1]
+    batch = len(ns)
+    host = np.full((batch, n_max, n_max), 3.5)
+    ref = []
+    for b, nb in enumerate(ns):
+        if nb == 0:
+            ref.append(None)
+            continue
+        A = I.potrf_problem(f"panel-{b}", nb, 1)[0]
+        if b == 4:
+            A[70, 70] = -1.0          # not positive definite: fails in the first panel
+        if b == 6:
+            A[200, 200] = -50.0 * nb  # fails in the second panel
+        host[b, :nb, :nb] = np.triu(A) + np.tril(np.full((nb, nb), 3.5), -1)
+        ref.append(A)
+    dA = tla.to_device_cm(host, ld=ld)
+    ops = tla.Operands(n_max, dA)
+    ops.n.copy_(torch.tensor(ns, dtype=torch.int32))
+    h.set_plan("potrf", "f64", (1, 16, 1, 4, 0))
+    print("potrf panels uneven", flush=True)
+    tla.potrf(h, dA, ops=ops)
+    torch.cuda.synchronize()
+    h.set_plan("potrf", "f64", None)
+    X = tla.from_device_cm(dA, n_max)
+    info = ops.info.cpu().numpy()
+    for b, nb in enumerate(ns):
+        if nb == 0:
+            assert info[b] == 0 and np.array_equal(X[b], host[b])
+            continue
+        Xr, ir = orc.potrf_batch(ref[b][None])
+        assert info[b] == ir[0], (b, info[b], ir[0])
+        il = np.tril_indices(nb, -1)
+        assert np.all(X[b, :nb, :nb][il] == 3.5)
+        # nothing outside the instance's n x n block is touched
+        assert np.all(X[b, nb:, :] == 3.5) and np.all(X[b, :, nb:] == 3.5)
+        if ir[0] == 0:
+            assert rel_err(np.triu(X[b, :nb, :nb])[None], Xr).max() <= 1e-12, b
