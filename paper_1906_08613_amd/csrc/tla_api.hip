@@ -372,6 +372,8 @@ tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& 
     // left-looking Cholesky: block panels, each update one batched product
     // (from n = 384; at n = 256 the one-workgroup kernel measured faster)
     if (op == TLA_POTRF && p.variant == 1 && a.n_max >= 384) return potrf_panel(h, a);
+    // tile-wavefront Sylvester: the same wavefront over 128 x 128 blocks
+    if (op == TLA_TRSYL && p.variant == 0 && a.n_max >= 384) return trsyl_blocks(h, a);
     a.ntmax = (a.n_max + 15) / 16;
     KFn fn64 = large_kernel(op, p.variant);
     if (!fn64) return TLA_E_UNSUPPORTED;

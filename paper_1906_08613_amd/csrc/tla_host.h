@@ -88,6 +88,8 @@ tla_status noalloc_init(int device);
 tla_status launch(tla_ctx* h, int op, int prec, const tla_plan& p, const KArgs& a);
 // Large FP64 Cholesky, left-looking by block panels (tla_panel.hip).
 tla_status potrf_panel(tla_ctx* h, const KArgs& a);
+// Large FP64 Sylvester by a wavefront over 128 x 128 blocks (tla_panel.hip).
+tla_status trsyl_blocks(tla_ctx* h, const KArgs& a);
 size_t lds_bytes(int op, int prec, int tb, int nw, int ntmax, int placement);
 int choose_placement(tla_ctx* h, int op, int prec, const tla_plan& p, int ntmax, size_t* lds);
 bool plan_valid(int op, const tla_plan& p);

@@ -286,7 +286,252 @@ __global__ __launch_bounds__(kTsNW * 64) void k_panel_trsm(SolveArgs g) {
 
 size_t panel_trsm_lds() { return ((size_t)kTsNT * (kTsNT + 1) / 2 * kTsTile + (size_t)kTsNW * kTsScr) * sizeof(double); }
 
+// ======================================================= Sylvester by blocks
+// L X + X U = C for the large sizes as a wavefront over NB x NB blocks (NB = 128): the
+// blocks (I, J) with I + J = d are independent once the earlier anti-diagonals
+// are solved, and each needs
+//   C_IJ -= L_{I,<I} X_{<I,J} + X_{I,<J} U_{<J,J}     (update)
+//   L_II X_IJ + X_IJ U_JJ = C_IJ                        (block solve)
+// Each anti-diagonal is two launches over the whole batch: the updates as
+// batched FP64 matrix-core products (two k-loops into one accumulator), then
+// the block solves, one workgroup per block, by the tile wavefront of the
+// in-place kernels on rectangular blocks (the last block row and column are
+// shorter when NB does not divide n).
+
+struct SylArgs {
+  int batch, nb, d;
+  const int* n;          // order in use (0: skip the instance)
+  const double* const* l;
+  const int* ldl;
+  const double* const* u;
+  const int* ldu;
+  double* const* c;
+  const int* ldc;
+};
+
+// grid ((nb / 64)^2 sub-blocks of 64 x 64, block row I, instance)
+__global__ __launch_bounds__(256) void k_bgemm_syl(SylArgs g) {
+  __shared__ double sA[kBk * kBld];
+  __shared__ double sB[kBk * kBld];
+  const int b = blockIdx.z, I = blockIdx.y, J = g.d - I;
+  const int n = g.n[b], nb = g.nb;
+  const int P = (n + nb - 1) / nb;
+  if (J < 0 || I >= P || J >= P) return;
+  const int mI = n - I * nb < nb ? n - I * nb : nb, nJ = n - J * nb < nb ? n - J * nb : nb;
+  const int sb = nb / kBg;  // sub-blocks of 64 per block dimension
+  const int i0 = ((int)blockIdx.x / sb) * kBg, j0 = ((int)blockIdx.x % sb) * kBg;
+  if (i0 >= mI || j0 >= nJ) return;
+  const int ldl = g.ldl[b], ldu = g.ldu[b], ldc = g.ldc[b];
+  const gbl_t<double>* L = to_gbl(g.l[b]);
+  const gbl_t<double>* U = to_gbl(g.u[b]);
+  gbl_t<double>* X = to_gbl(g.c[b]);
+  const int t = threadIdx.x, l = lane_id(), w = wave_id();
+  const int rI = I * nb + i0, cJ = J * nb + j0;  // first row / column of the output block
+  const int mr = mI - i0, mc = nJ - j0;          // its valid extent
+  typedef double d4v __attribute__((ext_vector_type(4)));
+  d4v acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = d4v{0.0, 0.0, 0.0, 0.0};
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32, i16 = l & 15, kq = l >> 4;
+  // A operand (i, k) at A[i + k lda] (16 consecutive-k panels, rows along
+  // the lanes: e & 63 is the row, e >> 6 the k); B operand (k, j) at
+  // B[k + j ldb] (e & 15 the k, e >> 4 the column)
+  for (int pass = 0; pass < 2; ++pass) {
+    const gbl_t<double>* A = pass == 0 ? L + rI : X + rI;
+    const int lda = pass == 0 ? ldl : ldc;
+    const gbl_t<double>* B = pass == 0 ? X + (size_t)cJ * ldc : U + (size_t)cJ * ldu;
+    const int ldb = pass == 0 ? ldc : ldu;
+    const int K = pass == 0 ? I * nb : J * nb;
+    if (K == 0) continue;
+    double ra[4], rb[4];
+    auto fetch = [&](int kt) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = t + 256 * r;
+        const int ai = e & 63, ak = e >> 6;
+        const int aic = ai < mr ? ai : mr - 1;
+        const double va = A[aic + (size_t)(kt + ak) * lda];
+        ra[r] = ai < mr ? va : 0.0;
+        const int bk = e & 15, bj = e >> 4;
+        const int bjc = bj < mc ? bj : mc - 1;
+        const double vb = B[(kt + bk) + (size_t)bjc * ldb];
+        rb[r] = bj < mc ? vb : 0.0;
+      }
+    };
+    fetch(0);
+    for (int kt = 0; kt < K; kt += kBk) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = t + 256 * r;
+        sA[(e >> 6) * kBld + (e & 63)] = ra[r];
+        sB[(e & 15) * kBld + (e >> 4)] = rb[r];
+      }
+      __syncthreads();
+      if (kt + kBk < K) fetch(kt + kBk);
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) {
+        const int kr = (4 * k4 + kq) * kBld;
+        double fa[2], fb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) fa[a] = sA[kr + wr + 16 * a + i16];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) fb[c] = sB[kr + wc + 16 * c + i16];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = wr + 16 * a + kq + 4 * r, j = wc + 16 * c + i16;
+        if (i < mr && j < mc) {
+          gbl_t<double>* p = X + (rI + i) + (size_t)(cJ + j) * ldc;
+          *p = *p - acc[a][c][r];
+        }
+      }
+}
+
+// In/out view of an nr x nc block of a column-major matrix: reads outside
+// return 0, writes there are dropped.
+struct BlockIO {
+  double* p;
+  int ld, nr, nc, r0, c0;
+  TLA_DI double operator()(int i, int j) const {
+    const int r = r0 + i, c = c0 + j;
+    const int rr = r < nr ? r : nr - 1, cc = c < nc ? c : nc - 1;
+    const double raw = to_gbl(p)[rr + (size_t)cc * ld];
+    return (r < nr && c < nc) ? raw : 0.0;
+  }
+  TLA_DI void store(int i, int j, double v) const {
+    const int r = r0 + i, c = c0 + j;
+    if (r < nr && c < nc) to_gbl(p)[r + (size_t)c * ld] = v;
+  }
+  TLA_DI void fence() const { __threadfence_block(); }
+  TLA_DI BlockIO sub(int i0, int j0) const {
+    BlockIO v = *this;
+    v.r0 += i0;
+    v.c0 += j0;
+    return v;
+  }
+};
+
+constexpr int kSbNW = 4;    // (8 waves measured slower)
+constexpr int kSylNB = 128;  // block order (a multiple of 64)
+
+// grid (block row I, instance): the block (I, d - I) by the tile wavefront
+__global__ __launch_bounds__(kSbNW * 64) void k_syl_blocks(SylArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.y, I = blockIdx.x, J = g.d - I;
+  const int n = g.n[b], nb = g.nb;
+  const int P = (n + nb - 1) / nb;
+  if (J < 0 || I >= P || J >= P) return;
+  const int mI = n - I * nb < nb ? n - I * nb : nb, nJ = n - J * nb < nb ? n - J * nb : nb;
+  const int ldl = g.ldl[b], ldu = g.ldu[b], ldc = g.ldc[b];
+  const GView<double> Lb = gview<double>(g.l[b] + (size_t)I * nb * (1 + (size_t)ldl), ldl, mI, -1);
+  const GView<double> Ub = gview<double>(g.u[b] + (size_t)J * nb * (1 + (size_t)ldu), ldu, nJ, +1);
+  const BlockIO X{g.c[b] + (size_t)I * nb + (size_t)J * nb * ldc, ldc, mI, nJ, 0, 0};
+  lds_t<double>* wbuf = to_lds(reinterpret_cast<double*>(smem) + wave_id() * wave_scratch(16));
+  typedef Gemm<double, 16, ENG_MFMA> G;
+  const int ntr = (mI + 15) / 16, ntc = (nJ + 15) / 16, w = wave_id();
+  for (int dd = 0; dd <= ntr + ntc - 2; ++dd) {
+    const int lo = dd - ntc + 1 > 0 ? dd - ntc + 1 : 0, hi = dd < ntr - 1 ? dd : ntr - 1;
+    for (int Ii = lo + w; Ii <= hi; Ii += kSbNW) {
+      const int Jj = dd - Ii;
+      const auto k = sylv_fetch<double, 16>(Lb.sub(16 * Ii, 16 * Ii), Ub.sub(16 * Jj, 16 * Jj));
+      Tile<double, 16> c;
+      tload(c, X.sub(16 * Ii, 16 * Jj));
+      gemm_sum<G>(c, 0, Ii, [&](int K) { return Lb.sub(16 * Ii, 16 * K); }, [&](int K) { return X.sub(16 * K, 16 * Jj); });
+      gemm_sum<G>(c, 0, Jj, [&](int K) { return X.sub(16 * Ii, 16 * K); }, [&](int K) { return Ub.sub(16 * K, 16 * Jj); });
+      sylv_solve<double, 16>(c, k, wbuf, mI - 16 * Ii, nJ - 16 * Jj);
+      tstore(c, X.sub(16 * Ii, 16 * Jj));
+    }
+    __syncthreads();
+  }
+}
+
+// per instance: argument checks, the first zero denominator l_ii + u_jj
+// (column-major order, as the in-place kernels report it), refinement record
+struct SylPrep {
+  int n_max;
+  const int* n_in;
+  const double* const* l;
+  const int* ldl;
+  const double* const* u;
+  const int* ldu;
+  const int* ldc;
+  int* n_use;
+  int* info;
+  tla_stat* stat;
+};
+
+__global__ __launch_bounds__(256) void k_syl_prep(SylPrep g) {
+  __shared__ int s_info;
+  const int b = blockIdx.x;
+  const int n = g.n_in[b];
+  int st = 0;
+  if (n < 0 || n > g.n_max) st = -1;
+  else if (g.ldl[b] < (n > 1 ? n : 1) || g.ldu[b] < (n > 1 ? n : 1) || g.ldc[b] < (n > 1 ? n : 1)) st = -2;
+  if (threadIdx.x == 0) s_info = INT_MAX;
+  __syncthreads();
+  if (st == 0 && n > 0)
+    scan_zero_denoms(gview<double>(g.l[b], g.ldl[b], n, -1), gview<double>(g.u[b], g.ldu[b], n, +1), n, false,
+                     &s_info);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (st == 0 && s_info != INT_MAX) st = s_info;
+    g.info[b] = st;
+    g.n_use[b] = st == 0 ? n : 0;
+    if (g.stat) {
+      g.stat[b].iters = 0;
+      g.stat[b].flags = 0;
+      g.stat[b].eta = 0.0;
+    }
+  }
+}
+
 }  // namespace
+
+// Large FP64 Sylvester by the block wavefront; a as for the in-place kernels.
+tla_status trsyl_blocks(tla_ctx* h, const KArgs& a) {
+  const int batch = a.batch, nb = kSylNB;
+  const size_t bytes = (size_t)batch * sizeof(int);
+  if (bytes > h->panel_bytes) {
+    if (h->panel_work) {
+      PN_HIP(hipStreamSynchronize(h->stream));
+      hipFree(h->panel_work);
+      h->panel_work = nullptr;
+      h->panel_bytes = 0;
+    }
+    if (hipMalloc(&h->panel_work, bytes) != hipSuccess) return TLA_E_NOMEM;
+    h->panel_bytes = bytes;
+  }
+  int* n_use = reinterpret_cast<int*>(h->panel_work);
+  SylPrep sp{a.n_max, a.n, a.a, a.lda, a.b, a.ldb, a.ldc, n_use, a.info, a.stat};
+  hipLaunchKernelGGL(k_syl_prep, dim3(batch), dim3(256), 0, h->stream, sp);
+  PN_HIP(hipGetLastError());
+  const int P = (a.n_max + nb - 1) / nb;
+  const size_t lds = (size_t)kSbNW * wave_scratch(16) * sizeof(double);
+  for (int d = 0; d <= 2 * P - 2; ++d) {
+    SylArgs ga{batch, nb, d, n_use, a.a, a.lda, a.b, a.ldb, a.c, a.ldc};
+    if (d > 0) {
+      hipLaunchKernelGGL(k_bgemm_syl, dim3((nb / kBg) * (nb / kBg), P, batch), dim3(256), 0, h->stream, ga);
+      PN_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_syl_blocks, dim3(P, batch), dim3(64 * kSbNW), lds, h->stream, ga);
+    PN_HIP(hipGetLastError());
+  }
+  return TLA_OK;
+}
 
 // Large FP64 Cholesky by block panels; a as for the in-place kernels.
 tla_status potrf_panel(tla_ctx* h, const KArgs& a) {

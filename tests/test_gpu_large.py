@@ -174,3 +174,38 @@ def test_large_potrf_panels_uneven_n_and_failures(h, orc):
         assert np.all(X[b, nb:, :] == 3.5) and np.all(X[b, :, nb:] == 3.5)
         if ir[0] == 0:
             assert rel_err(np.triu(X[b, :nb, :nb])[None], Xr).max() <= 1e-12, b
+
+
+def test_large_trsyl_blocks_uneven_n_and_zero_denominator(h, orc):
+    # the tile-wavefront large Sylvester runs as a wavefront over 128 x 128
+    # blocks: orders below, at and across block edges in one batch, padded
+    # leading dimensions, and an instance with a zero denominator
+    n_max, ld = 400, 403
+    ns = [400, 0, 129, 385, 200, 1, 256]
+    batch = len(ns)
+    Lh, Uh, Ch = (np.full((batch, n_max, n_max), 7.0) for _ in range(3))
+    for b, nb in enumerate(ns):
+        if nb == 0:
+            continue
+        L, U, C = I.trsyl_problem(f"blocks-{b}", nb, 1)
+        if b == 4:
+            L[0, 150, 150] = 1.5
+            U[0, 170, 170] = -1.5   # l_150,150 + u_170,170 = 0
+        Lh[b, :nb, :nb], Uh[b, :nb, :nb], Ch[b, :nb, :nb] = L[0], U[0], C[0]
+    dL, dU, dC = (tla.to_device_cm(M, ld=ld) for M in (Lh, Uh, Ch))
+    ops = tla.Operands(n_max, dL, dU, dC)
+    ops.n.copy_(torch.tensor(ns, dtype=torch.int32))
+    print("trsyl blocks uneven", flush=True)
+    tla.trsyl(h, dL, dU, dC, ops=ops)
+    torch.cuda.synchronize()
+    X = tla.from_device_cm(dC, n_max)
+    info = ops.info.cpu().numpy()
+    for b, nb in enumerate(ns):
+        if nb == 0:
+            assert info[b] == 0 and np.array_equal(X[b], Ch[b])
+            continue
+        Xr, ir = orc.trsyl_batch(Lh[b:b + 1, :nb, :nb], Uh[b:b + 1, :nb, :nb], Ch[b:b + 1, :nb, :nb])
+        assert info[b] == ir[0], (b, info[b], ir[0])
+        assert np.all(X[b, nb:, :] == 7.0) and np.all(X[b, :, nb:] == 7.0)
+        if ir[0] == 0:
+            assert rel_err(X[b, :nb, :nb][None], Xr).max() <= 1e-12, b
