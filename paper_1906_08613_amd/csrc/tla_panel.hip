@@ -8,7 +8,7 @@
 //   X(k0:k0+NB, k0+NB:n) = X_kk^{-T} A(k0:k0+NB, k0+NB:n)       panel solve
 //
 // The update carries almost all of the n^3/3 flops.  It runs as one batched
-// product over all instances (k_bgemm_chol: 64 x 64 output blocks per
+// product over all instances (k_bgemm_chol: 128 x 128 output blocks per
 // workgroup, 16-deep operand panels staged in LDS, FP64 matrix cores),
 // instead of tile products inside one workgroup per instance: a 16-wave
 // instance workgroup re-reads every operand tile from memory and keeps one
@@ -47,88 +47,103 @@ struct PanelArgs {
 
 // C(i, j) -= sum_k X(k, k0 + i) X(k, k0 + j) over k < k0, for
 // 0 <= i < min(nb, n - k0), i <= j < n - k0 (upper triangle only).
-// Grid (column blocks of 64, row blocks of 64, instances), 4 waves; wave w
-// computes the 32 x 32 quadrant (w >> 1, w & 1) of the block as 2 x 2 tiles.
+// Grid (column blocks of 128, row blocks of 128, instances), 4 waves.
 constexpr int kBg = 64, kBk = 16, kBld = kBg + 4;
 
-__global__ __launch_bounds__(256) void k_bgemm_chol(PanelArgs g) {
-  __shared__ double sA[kBk * kBld];
-  __shared__ double sB[kBk * kBld];
+// ---- batched product core: acc += A B for one 128 x 128 output block.
+// A (128 x K) is read either k-contiguous (element (i, k) at A[k + i lda],
+// AK) or row-contiguous (A[i + k lda]); B (K x 128) k-contiguous
+// (B[k + j ldb]).  Rows i >= mr of A and columns j >= mc of B read as zero;
+// K is a multiple of 16.  256 threads: wave w accumulates the 64 x 64
+// quadrant (w >> 1, w & 1) as 4 x 4 tiles on the FP64 matrix cores; 16-deep
+// panels of A and B are staged in LDS and the next pair is loaded into
+// registers while the current one is multiplied.
+constexpr int kCg = 128, kCld = kCg + 4;
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <bool AK>
+TLA_DI void bgemm128(d4v (&acc)[4][4], const gbl_t<double>* A, int lda, const gbl_t<double>* B, int ldb, int K,
+                     int mr, int mc, lds_t<double>* sA, lds_t<double>* sB) {
+  const int t = threadIdx.x, l = lane_id(), w = wave_id();
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64, i16 = l & 15, kq = l >> 4;
+  double ra[8], rb[8];
+  // element r of this thread: A row (t >> 4) + 16 r at k = t & 15 (AK) or row
+  // t & 127 at k = (t >> 7) + 2 r; B column (t >> 4) + 16 r at k = t & 15.
+  // One base pointer per operand; lanes outside the block load nothing.
+  const gbl_t<double>* pa = AK ? A + (t & 15) + (size_t)(t >> 4) * lda : A + (t & 127) + (size_t)(t >> 7) * lda;
+  const gbl_t<double>* pb = B + (t & 15) + (size_t)(t >> 4) * ldb;
+  const size_t sa = AK ? (size_t)16 * lda : (size_t)2 * lda, sb = (size_t)16 * ldb;
+  auto fetch = [&](int kt) {
+    const size_t ka = AK ? (size_t)kt : (size_t)kt * lda;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const bool ina = AK ? (t >> 4) + 16 * r < mr : (t & 127) < mr;
+      ra[r] = ina ? pa[ka + r * sa] : 0.0;
+      rb[r] = (t >> 4) + 16 * r < mc ? pb[kt + r * sb] : 0.0;
+    }
+  };
+  if (K <= 0) return;
+  fetch(0);
+  for (int kt = 0; kt < K; kt += kBk) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = t + 256 * r;
+      if constexpr (AK) sA[(e & 15) * kCld + (e >> 4)] = ra[r];
+      else sA[(e >> 7) * kCld + (e & 127)] = ra[r];
+      sB[(e & 15) * kCld + (e >> 4)] = rb[r];
+    }
+    __syncthreads();
+    if (kt + kBk < K) fetch(kt + kBk);
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) {
+      const int kr = (4 * k4 + kq) * kCld;
+      double fa[4], fb[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) fa[a] = sA[kr + wr + 16 * a + i16];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) fb[c] = sB[kr + wc + 16 * c + i16];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
+    }
+  }
+}
+
+TLA_DI void zero_acc(d4v (&acc)[4][4]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = d4v{0.0, 0.0, 0.0, 0.0};
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_bgemm_chol(PanelArgs g) {
+  __shared__ double sA[kBk * kCld];
+  __shared__ double sB[kBk * kCld];
   const int b = blockIdx.z;
   const int n = g.n[b];
   const int k0 = g.k0;
   if (n <= k0) return;
   const int M = n - k0 < g.nb ? n - k0 : g.nb, N = n - k0;
-  const int i0 = blockIdx.y * kBg, j0 = blockIdx.x * kBg;
-  if (i0 >= M || j0 >= N || i0 > j0 + kBg - 1) return;  // nothing of the upper triangle here
+  const int i0 = blockIdx.y * kCg, j0 = blockIdx.x * kCg;
+  if (i0 >= M || j0 >= N || i0 > j0 + kCg - 1) return;  // nothing of the upper triangle here
   const int ld = g.ld[b];
   const gbl_t<double>* X = to_gbl(static_cast<const double*>(g.x[b]));
-  const int t = threadIdx.x, l = lane_id(), w = wave_id();
-  // this thread's four elements of each 16 x 64 operand panel: k = e & 15,
-  // column e >> 4 (16 consecutive k of one column per 16 lanes: 128 B)
-  const gbl_t<double>* pa[4];
-  const gbl_t<double>* pb[4];
-  bool ma[4], mb[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int e = t + 256 * r, kk = e & 15, c = e >> 4;
-    const int ia = i0 + c < M ? i0 + c : M - 1, jb = j0 + c < N ? j0 + c : N - 1;
-    ma[r] = i0 + c < M;
-    mb[r] = j0 + c < N;
-    pa[r] = X + kk + (size_t)(k0 + ia) * ld;
-    pb[r] = X + kk + (size_t)(k0 + jb) * ld;
-  }
-  double ra[4], rb[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    ra[r] = ma[r] ? pa[r][0] : 0.0;
-    rb[r] = mb[r] ? pb[r][0] : 0.0;
-  }
-  typedef double d4v __attribute__((ext_vector_type(4)));
-  d4v acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) acc[a][c] = d4v{0.0, 0.0, 0.0, 0.0};
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32, i16 = l & 15, kq = l >> 4;
-  for (int kt = 0; kt < k0; kt += kBk) {
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int e = t + 256 * r, kk = e & 15, c = e >> 4;
-      sA[kk * kBld + c] = ra[r];
-      sB[kk * kBld + c] = rb[r];
-    }
-    __syncthreads();
-    if (kt + kBk < k0) {  // the next panel's loads overlap this panel's products
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        ra[r] = ma[r] ? pa[r][kt + kBk] : 0.0;
-        rb[r] = mb[r] ? pb[r][kt + kBk] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int k4 = 0; k4 < 4; ++k4) {
-      const int kr = (4 * k4 + kq) * kBld;
-      double fa[2], fb[2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) fa[a] = sA[kr + wr + 16 * a + i16];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) fb[c] = sB[kr + wc + 16 * c + i16];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
-    }
-  }
+  d4v acc[4][4];
+  zero_acc(acc);
+  // A(i, k) = X(k, k0 + i0 + i), B(k, j) = X(k, k0 + j0 + j), k < k0
+  bgemm128<true>(acc, X + (size_t)(k0 + i0) * ld, ld, X + (size_t)(k0 + j0) * ld, ld, k0, M - i0, N - j0, to_lds(sA),
+                 to_lds(sB));
   gbl_t<double>* C = to_gbl(g.x[b]);
+  const int l = lane_id(), w = wave_id(), wr = (w >> 1) * 64, wc = (w & 1) * 64;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wr + 16 * a + kq + 4 * r, j = j0 + wc + 16 * c + i16;
+        const int i = i0 + wr + 16 * a + (l >> 4) + 4 * r, j = j0 + wc + 16 * c + (l & 15);
         if (i < M && j < N && i <= j) {
           gbl_t<double>* p = C + (k0 + i) + (size_t)(k0 + j) * ld;
           *p = *p - acc[a][c][r];
@@ -309,92 +324,40 @@ struct SylArgs {
   const int* ldc;
 };
 
-// grid ((nb / 64)^2 sub-blocks of 64 x 64, block row I, instance)
-__global__ __launch_bounds__(256) void k_bgemm_syl(SylArgs g) {
-  __shared__ double sA[kBk * kBld];
-  __shared__ double sB[kBk * kBld];
+// grid (1, block row I, instance): the update of block (I, d - I), NB = 128
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_bgemm_syl(SylArgs g) {
+  __shared__ double sA[kBk * kCld];
+  __shared__ double sB[kBk * kCld];
   const int b = blockIdx.z, I = blockIdx.y, J = g.d - I;
   const int n = g.n[b], nb = g.nb;
   const int P = (n + nb - 1) / nb;
   if (J < 0 || I >= P || J >= P) return;
   const int mI = n - I * nb < nb ? n - I * nb : nb, nJ = n - J * nb < nb ? n - J * nb : nb;
-  const int sb = nb / kBg;  // sub-blocks of 64 per block dimension
-  const int i0 = ((int)blockIdx.x / sb) * kBg, j0 = ((int)blockIdx.x % sb) * kBg;
-  if (i0 >= mI || j0 >= nJ) return;
   const int ldl = g.ldl[b], ldu = g.ldu[b], ldc = g.ldc[b];
   const gbl_t<double>* L = to_gbl(g.l[b]);
   const gbl_t<double>* U = to_gbl(g.u[b]);
   gbl_t<double>* X = to_gbl(g.c[b]);
-  const int t = threadIdx.x, l = lane_id(), w = wave_id();
-  const int rI = I * nb + i0, cJ = J * nb + j0;  // first row / column of the output block
-  const int mr = mI - i0, mc = nJ - j0;          // its valid extent
-  typedef double d4v __attribute__((ext_vector_type(4)));
-  d4v acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) acc[a][c] = d4v{0.0, 0.0, 0.0, 0.0};
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32, i16 = l & 15, kq = l >> 4;
-  // A operand (i, k) at A[i + k lda] (16 consecutive-k panels, rows along
-  // the lanes: e & 63 is the row, e >> 6 the k); B operand (k, j) at
-  // B[k + j ldb] (e & 15 the k, e >> 4 the column)
+  const int rI = I * nb, cJ = J * nb;
+  d4v acc[4][4];
+  zero_acc(acc);
+  // L_{I,<I} X_{<I,J}, then X_{I,<J} U_{<J,J} (one copy of the core: a
+  // loop, not two inlined calls, keeps the registers within budget)
+#pragma unroll 1
   for (int pass = 0; pass < 2; ++pass) {
     const gbl_t<double>* A = pass == 0 ? L + rI : X + rI;
-    const int lda = pass == 0 ? ldl : ldc;
     const gbl_t<double>* B = pass == 0 ? X + (size_t)cJ * ldc : U + (size_t)cJ * ldu;
-    const int ldb = pass == 0 ? ldc : ldu;
-    const int K = pass == 0 ? I * nb : J * nb;
-    if (K == 0) continue;
-    double ra[4], rb[4];
-    auto fetch = [&](int kt) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int e = t + 256 * r;
-        const int ai = e & 63, ak = e >> 6;
-        const int aic = ai < mr ? ai : mr - 1;
-        const double va = A[aic + (size_t)(kt + ak) * lda];
-        ra[r] = ai < mr ? va : 0.0;
-        const int bk = e & 15, bj = e >> 4;
-        const int bjc = bj < mc ? bj : mc - 1;
-        const double vb = B[(kt + bk) + (size_t)bjc * ldb];
-        rb[r] = bj < mc ? vb : 0.0;
-      }
-    };
-    fetch(0);
-    for (int kt = 0; kt < K; kt += kBk) {
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int e = t + 256 * r;
-        sA[(e >> 6) * kBld + (e & 63)] = ra[r];
-        sB[(e & 15) * kBld + (e >> 4)] = rb[r];
-      }
-      __syncthreads();
-      if (kt + kBk < K) fetch(kt + kBk);
-#pragma unroll
-      for (int k4 = 0; k4 < 4; ++k4) {
-        const int kr = (4 * k4 + kq) * kBld;
-        double fa[2], fb[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) fa[a] = sA[kr + wr + 16 * a + i16];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) fb[c] = sB[kr + wc + 16 * c + i16];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int c = 0; c < 2; ++c)
-            acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
-      }
-    }
+    bgemm128<false>(acc, A, pass == 0 ? ldl : ldc, B, pass == 0 ? ldc : ldu, (pass == 0 ? I : J) * nb, mI, nJ,
+                    to_lds(sA), to_lds(sB));
   }
+  const int l = lane_id(), w = wave_id(), wr = (w >> 1) * 64, wc = (w & 1) * 64;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = wr + 16 * a + kq + 4 * r, j = wc + 16 * c + i16;
-        if (i < mr && j < mc) {
+        const int i = wr + 16 * a + (l >> 4) + 4 * r, j = wc + 16 * c + (l & 15);
+        if (i < mI && j < nJ) {
           gbl_t<double>* p = X + (rI + i) + (size_t)(cJ + j) * ldc;
           *p = *p - acc[a][c][r];
         }
@@ -426,7 +389,7 @@ struct BlockIO {
 };
 
 constexpr int kSbNW = 4;    // (8 waves measured slower)
-constexpr int kSylNB = 128;  // block order (a multiple of 64)
+constexpr int kSylNB = 128;  // block order (one 128 x 128 update block)
 
 // grid (block row I, instance): the block (I, d - I) by the tile wavefront
 __global__ __launch_bounds__(kSbNW * 64) void k_syl_blocks(SylArgs g) {
@@ -524,7 +487,7 @@ tla_status trsyl_blocks(tla_ctx* h, const KArgs& a) {
   for (int d = 0; d <= 2 * P - 2; ++d) {
     SylArgs ga{batch, nb, d, n_use, a.a, a.lda, a.b, a.ldb, a.c, a.ldc};
     if (d > 0) {
-      hipLaunchKernelGGL(k_bgemm_syl, dim3((nb / kBg) * (nb / kBg), P, batch), dim3(256), 0, h->stream, ga);
+      hipLaunchKernelGGL(k_bgemm_syl, dim3(1, P, batch), dim3(256), 0, h->stream, ga);
       PN_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_syl_blocks, dim3(P, batch), dim3(64 * kSbNW), lds, h->stream, ga);
@@ -568,7 +531,7 @@ tla_status potrf_panel(tla_ctx* h, const KArgs& a) {
   for (int k0 = 0; k0 < a.n_max; k0 += nb) {
     if (k0 > 0) {
       PanelArgs ga{batch, a.n_max, k0, nb, n_use, a.c, a.ldc};
-      const dim3 grid((a.n_max - k0 + kBg - 1) / kBg, (nb + kBg - 1) / kBg, batch);
+      const dim3 grid((a.n_max - k0 + kCg - 1) / kCg, (nb + kCg - 1) / kCg, batch);
       hipLaunchKernelGGL(k_bgemm_chol, grid, dim3(256), 0, h->stream, ga);
       PN_HIP(hipGetLastError());
     }
