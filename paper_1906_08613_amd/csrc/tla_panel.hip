@@ -8,7 +8,7 @@
 //   X(k0:k0+NB, k0+NB:n) = X_kk^{-T} A(k0:k0+NB, k0+NB:n)       panel solve
 //
 // The update carries almost all of the n^3/3 flops.  It runs as one batched
-// product over all instances (k_bgemm_chol: 128 x 128 output blocks per
+// product over all instances (k_bgemm_chol: 64 x 64 output blocks per
 // workgroup, 16-deep operand panels staged in LDS, FP64 matrix cores),
 // instead of tile products inside one workgroup per instance: a 16-wave
 // instance workgroup re-reads every operand tile from memory and keeps one
@@ -48,36 +48,41 @@ struct PanelArgs {
 // C(i, j) -= sum_k X(k, k0 + i) X(k, k0 + j) over k < k0, for
 // 0 <= i < min(nb, n - k0), i <= j < n - k0 (upper triangle only).
 // Grid (column blocks of 128, row blocks of 128, instances), 4 waves.
-constexpr int kBg = 64, kBk = 16, kBld = kBg + 4;
+constexpr int kBk = 16;  // depth of the staged operand panels
 
-// ---- batched product core: acc += A B for one 128 x 128 output block.
-// A (128 x K) is read either k-contiguous (element (i, k) at A[k + i lda],
-// AK) or row-contiguous (A[i + k lda]); B (K x 128) k-contiguous
-// (B[k + j ldb]).  Rows i >= mr of A and columns j >= mc of B read as zero;
-// K is a multiple of 16.  256 threads: wave w accumulates the 64 x 64
-// quadrant (w >> 1, w & 1) as 4 x 4 tiles on the FP64 matrix cores; 16-deep
-// panels of A and B are staged in LDS and the next pair is loaded into
-// registers while the current one is multiplied.
-constexpr int kCg = 128, kCld = kCg + 4;
+// ---- batched product core: acc += A B for one BM x BM output block
+// (BM = 64 or 128).  A (BM x K) is read either k-contiguous (element (i, k)
+// at A[k + i lda], AK) or row-contiguous (A[i + k lda]); B (K x BM)
+// k-contiguous (B[k + j ldb]).  Rows i >= mr of A and columns j >= mc of B
+// read as zero; K is a multiple of 16.  256 threads: wave w accumulates the
+// quadrant (w >> 1, w & 1) as TW x TW tiles of 16 x 16 on the FP64 matrix
+// cores; 16-deep panels of A and B are staged in LDS and the next pair is
+// loaded into registers while the current one is multiplied.
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-template <bool AK>
-TLA_DI void bgemm128(d4v (&acc)[4][4], const gbl_t<double>* A, int lda, const gbl_t<double>* B, int ldb, int K,
-                     int mr, int mc, lds_t<double>* sA, lds_t<double>* sB) {
+template <int BM>
+struct Core {
+  static constexpr int TW = BM / 32, LD = BM + 4, E = BM / 16;  // tiles per wave dim, LDS stride, loads per thread
+};
+
+template <int BM, bool AK>
+TLA_DI void bgemm_core(d4v (&acc)[BM / 32][BM / 32], const gbl_t<double>* A, int lda, const gbl_t<double>* B,
+                       int ldb, int K, int mr, int mc, lds_t<double>* sA, lds_t<double>* sB) {
+  constexpr int TW = Core<BM>::TW, LD = Core<BM>::LD, E = Core<BM>::E, RS = 256 / BM;
   const int t = threadIdx.x, l = lane_id(), w = wave_id();
-  const int wr = (w >> 1) * 64, wc = (w & 1) * 64, i16 = l & 15, kq = l >> 4;
-  double ra[8], rb[8];
+  const int wr = (w >> 1) * (BM / 2), wc = (w & 1) * (BM / 2), i16 = l & 15, kq = l >> 4;
+  double ra[E], rb[E];
   // element r of this thread: A row (t >> 4) + 16 r at k = t & 15 (AK) or row
-  // t & 127 at k = (t >> 7) + 2 r; B column (t >> 4) + 16 r at k = t & 15.
+  // t % BM at k = t / BM + RS r; B column (t >> 4) + 16 r at k = t & 15.
   // One base pointer per operand; lanes outside the block load nothing.
-  const gbl_t<double>* pa = AK ? A + (t & 15) + (size_t)(t >> 4) * lda : A + (t & 127) + (size_t)(t >> 7) * lda;
+  const gbl_t<double>* pa = AK ? A + (t & 15) + (size_t)(t >> 4) * lda : A + (t % BM) + (size_t)(t / BM) * lda;
   const gbl_t<double>* pb = B + (t & 15) + (size_t)(t >> 4) * ldb;
-  const size_t sa = AK ? (size_t)16 * lda : (size_t)2 * lda, sb = (size_t)16 * ldb;
+  const size_t sa = AK ? (size_t)16 * lda : (size_t)RS * lda, sb = (size_t)16 * ldb;
   auto fetch = [&](int kt) {
     const size_t ka = AK ? (size_t)kt : (size_t)kt * lda;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const bool ina = AK ? (t >> 4) + 16 * r < mr : (t & 127) < mr;
+    for (int r = 0; r < E; ++r) {
+      const bool ina = AK ? (t >> 4) + 16 * r < mr : (t % BM) < mr;
       ra[r] = ina ? pa[ka + r * sa] : 0.0;
       rb[r] = (t >> 4) + 16 * r < mc ? pb[kt + r * sb] : 0.0;
     }
@@ -87,60 +92,64 @@ TLA_DI void bgemm128(d4v (&acc)[4][4], const gbl_t<double>* A, int lda, const gb
   for (int kt = 0; kt < K; kt += kBk) {
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < E; ++r) {
       const int e = t + 256 * r;
-      if constexpr (AK) sA[(e & 15) * kCld + (e >> 4)] = ra[r];
-      else sA[(e >> 7) * kCld + (e & 127)] = ra[r];
-      sB[(e & 15) * kCld + (e >> 4)] = rb[r];
+      if constexpr (AK) sA[(e & 15) * LD + (e >> 4)] = ra[r];
+      else sA[(e / BM) * LD + (e % BM)] = ra[r];
+      sB[(e & 15) * LD + (e >> 4)] = rb[r];
     }
     __syncthreads();
     if (kt + kBk < K) fetch(kt + kBk);
 #pragma unroll
     for (int k4 = 0; k4 < 4; ++k4) {
-      const int kr = (4 * k4 + kq) * kCld;
-      double fa[4], fb[4];
+      const int kr = (4 * k4 + kq) * LD;
+      double fa[TW], fb[TW];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) fa[a] = sA[kr + wr + 16 * a + i16];
+      for (int a = 0; a < TW; ++a) fa[a] = sA[kr + wr + 16 * a + i16];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) fb[c] = sB[kr + wc + 16 * c + i16];
+      for (int c = 0; c < TW; ++c) fb[c] = sB[kr + wc + 16 * c + i16];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < TW; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
+        for (int c = 0; c < TW; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
     }
   }
 }
 
-TLA_DI void zero_acc(d4v (&acc)[4][4]) {
+template <int TW>
+TLA_DI void zero_acc(d4v (&acc)[TW][TW]) {
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < TW; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < TW; ++c) acc[a][c] = d4v{0.0, 0.0, 0.0, 0.0};
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_bgemm_chol(PanelArgs g) {
-  __shared__ double sA[kBk * kCld];
-  __shared__ double sB[kBk * kCld];
+constexpr int kCholBM = 64;  // (128 measured 8% slower: too few blocks late in the factorisation)
+
+__global__ __launch_bounds__(256) void k_bgemm_chol(PanelArgs g) {
+  constexpr int BM = kCholBM, TW = Core<BM>::TW;
+  __shared__ double sA[kBk * Core<BM>::LD];
+  __shared__ double sB[kBk * Core<BM>::LD];
   const int b = blockIdx.z;
   const int n = g.n[b];
   const int k0 = g.k0;
   if (n <= k0) return;
   const int M = n - k0 < g.nb ? n - k0 : g.nb, N = n - k0;
-  const int i0 = blockIdx.y * kCg, j0 = blockIdx.x * kCg;
-  if (i0 >= M || j0 >= N || i0 > j0 + kCg - 1) return;  // nothing of the upper triangle here
+  const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BM;
+  if (i0 >= M || j0 >= N || i0 > j0 + BM - 1) return;  // nothing of the upper triangle here
   const int ld = g.ld[b];
   const gbl_t<double>* X = to_gbl(static_cast<const double*>(g.x[b]));
-  d4v acc[4][4];
-  zero_acc(acc);
+  d4v acc[TW][TW];
+  zero_acc<TW>(acc);
   // A(i, k) = X(k, k0 + i0 + i), B(k, j) = X(k, k0 + j0 + j), k < k0
-  bgemm128<true>(acc, X + (size_t)(k0 + i0) * ld, ld, X + (size_t)(k0 + j0) * ld, ld, k0, M - i0, N - j0, to_lds(sA),
-                 to_lds(sB));
+  bgemm_core<BM, true>(acc, X + (size_t)(k0 + i0) * ld, ld, X + (size_t)(k0 + j0) * ld, ld, k0, M - i0, N - j0,
+                       to_lds(sA), to_lds(sB));
   gbl_t<double>* C = to_gbl(g.x[b]);
-  const int l = lane_id(), w = wave_id(), wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  const int l = lane_id(), w = wave_id(), wr = (w >> 1) * (BM / 2), wc = (w & 1) * (BM / 2);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < TW; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < TW; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = i0 + wr + 16 * a + (l >> 4) + 4 * r, j = j0 + wc + 16 * c + (l & 15);
@@ -326,8 +335,9 @@ struct SylArgs {
 
 // grid (1, block row I, instance): the update of block (I, d - I), NB = 128
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_bgemm_syl(SylArgs g) {
-  __shared__ double sA[kBk * kCld];
-  __shared__ double sB[kBk * kCld];
+  constexpr int BM = 128, TW = Core<BM>::TW;
+  __shared__ double sA[kBk * Core<BM>::LD];
+  __shared__ double sB[kBk * Core<BM>::LD];
   const int b = blockIdx.z, I = blockIdx.y, J = g.d - I;
   const int n = g.n[b], nb = g.nb;
   const int P = (n + nb - 1) / nb;
@@ -338,22 +348,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const gbl_t<double>* U = to_gbl(g.u[b]);
   gbl_t<double>* X = to_gbl(g.c[b]);
   const int rI = I * nb, cJ = J * nb;
-  d4v acc[4][4];
-  zero_acc(acc);
+  d4v acc[TW][TW];
+  zero_acc<TW>(acc);
   // L_{I,<I} X_{<I,J}, then X_{I,<J} U_{<J,J} (one copy of the core: a
   // loop, not two inlined calls, keeps the registers within budget)
 #pragma unroll 1
   for (int pass = 0; pass < 2; ++pass) {
     const gbl_t<double>* A = pass == 0 ? L + rI : X + rI;
     const gbl_t<double>* B = pass == 0 ? X + (size_t)cJ * ldc : U + (size_t)cJ * ldu;
-    bgemm128<false>(acc, A, pass == 0 ? ldl : ldc, B, pass == 0 ? ldc : ldu, (pass == 0 ? I : J) * nb, mI, nJ,
-                    to_lds(sA), to_lds(sB));
+    bgemm_core<BM, false>(acc, A, pass == 0 ? ldl : ldc, B, pass == 0 ? ldc : ldu, (pass == 0 ? I : J) * nb, mI,
+                          nJ, to_lds(sA), to_lds(sB));
   }
-  const int l = lane_id(), w = wave_id(), wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  const int l = lane_id(), w = wave_id(), wr = (w >> 1) * (BM / 2), wc = (w & 1) * (BM / 2);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < TW; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < TW; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = wr + 16 * a + (l >> 4) + 4 * r, j = wc + 16 * c + (l & 15);
@@ -531,7 +541,7 @@ tla_status potrf_panel(tla_ctx* h, const KArgs& a) {
   for (int k0 = 0; k0 < a.n_max; k0 += nb) {
     if (k0 > 0) {
       PanelArgs ga{batch, a.n_max, k0, nb, n_use, a.c, a.ldc};
-      const dim3 grid((a.n_max - k0 + kCg - 1) / kCg, (nb + kCg - 1) / kCg, batch);
+      const dim3 grid((a.n_max - k0 + kCholBM - 1) / kCholBM, (nb + kCholBM - 1) / kCholBM, batch);
       hipLaunchKernelGGL(k_bgemm_chol, grid, dim3(256), 0, h->stream, ga);
       PN_HIP(hipGetLastError());
     }
