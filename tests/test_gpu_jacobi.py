@@ -12,7 +12,7 @@ import pytest
 
 import paper_1906_08613_amd as tla
 from paper_1906_08613_amd import inputs as I
-from tests.gpu_util import rel_err
+from tests.gpu_util import elem_err, frob_err, rel_err
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -31,6 +31,12 @@ def h():
     yield hd
     hd.set_plan("trsyl", "mixed_bf16", None)
     hd.close()
+
+
+def fwd_ok(X, Xr, n, kappa):
+    # the forward-error bound from eta <= tau is normwise; entry by entry (each
+    # against its column's largest entry) it holds up to the factor sqrt(n)
+    return frob_err(X, Xr).max() <= fwd_tol(n, kappa) and elem_err(X, Xr).max() <= np.sqrt(n) * fwd_tol(n, kappa)
 
 
 def fwd_tol(n, kappa):
@@ -85,7 +91,7 @@ def test_jacobi_matches_oracle(h, orc, op, prec, kappa, n):
     st = tla.stat_view(ops.stat)
     assert np.all(ops.info.cpu().numpy() == ir)
     assert eta_fn(*mats, X).max() <= 1e-12, st
-    assert rel_err(X, Xr).max() <= fwd_tol(n, kappa)
+    assert fwd_ok(X, Xr, n, kappa)
     # these inputs contract fast: every instance converges in the mixed kernel
     assert np.all(st["flags"] & tla.STAT_CONVERGED), st
     assert st["iters"].max() <= 3 and np.all(st["eta"] <= TAU)

@@ -13,7 +13,7 @@ import pytest
 
 import paper_1906_08613_amd as tla
 from paper_1906_08613_amd import inputs as I
-from tests.gpu_util import rel_err
+from tests.gpu_util import elem_err, frob_err, rel_err
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -32,6 +32,12 @@ def h():
 
 
 TAU = 1e-13
+
+
+def fwd_ok(X, Xr, n, kappa):
+    # the forward-error bound from eta <= tau is normwise; entry by entry (each
+    # against its column's largest entry) it holds up to the factor sqrt(n)
+    return frob_err(X, Xr).max() <= fwd_tol(n, kappa) and elem_err(X, Xr).max() <= np.sqrt(n) * fwd_tol(n, kappa)
 
 
 def fwd_tol(n, kappa):
@@ -89,7 +95,7 @@ def test_mixed_matches_oracle(h, orc, op, prec, kappa, n):
     assert np.all(info == ir)
     eta = eta_fn(*mats, X)
     assert eta.max() <= 1e-12, (eta.max(), st)
-    assert rel_err(X, Xr).max() <= fwd_tol(n, kappa)
+    assert fwd_ok(X, Xr, n, kappa)
     # every instance either converged or was solved again in FP64
     ok = (st["flags"] & tla.STAT_CONVERGED) | (st["flags"] & (tla.STAT_FALLBACK | tla.STAT_BREAKDOWN))
     assert np.all(ok != 0)
@@ -204,7 +210,7 @@ def test_every_mixed_plan(h, orc, op):
                 continue
             X, ops = solve(h, op, mats, prec, plan)
             assert eta_fn(*mats, X).max() <= 1e-12, (prec, plan)
-            assert rel_err(X, Xr).max() <= fwd_tol(n, 1e3), (prec, plan)
+            assert fwd_ok(X, Xr, n, 1e3), (prec, plan)
 
 
 @pytest.mark.parametrize("op", ["potrf", "trsyl", "trlyap"])
@@ -220,7 +226,7 @@ def test_mixed_large_n_placements(h, orc, op, n):
         X, ops = solve(h, op, mats, prec)
         assert np.all(ops.info.cpu().numpy() == ir)
         assert eta_fn(*mats, X).max() <= 1e-12, prec
-        assert rel_err(X, Xr).max() <= fwd_tol(n, kappa), prec
+        assert fwd_ok(X, Xr, n, kappa), prec
 
 
 @pytest.mark.parametrize("op", ["potrf", "trsyl", "trlyap"])
@@ -238,7 +244,7 @@ def test_mixed_n128_condition_grid(h, orc, op, prec, kappa):
     st = tla.stat_view(ops.stat)
     assert np.all(ops.info.cpu().numpy() == ir)
     assert eta_fn(*mats, X).max() <= 1e-12, st
-    assert rel_err(X, Xr).max() <= fwd_tol(n, kappa)
+    assert fwd_ok(X, Xr, n, kappa)
     ok = (st["flags"] & tla.STAT_CONVERGED) | (st["flags"] & (tla.STAT_FALLBACK | tla.STAT_BREAKDOWN))
     assert np.all(ok != 0)
 
@@ -279,7 +285,7 @@ def test_mixed_above_lds_sizes(h, orc, op, n):
         st = tla.stat_view(ops.stat)
         assert np.all(st["flags"] & tla.STAT_CONVERGED), st["flags"]
         assert eta_fn(*mats, X).max() <= 1e-12, prec
-        assert rel_err(X, Xr).max() <= fwd_tol(n, kappa), prec
+        assert fwd_ok(X, Xr, n, kappa), prec
 
 
 @pytest.mark.skip(reason=SKIP_ABOVE_LDS)
