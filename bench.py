@@ -54,6 +54,10 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="skip autotuning the headline configuration first")
     p.add_argument("--table", default=None, help="load a tuning table instead of tuning")
     p.add_argument("--save-table", default=None, help="write the tuning table here")
+    p.add_argument("--traffic-summary", nargs=4, default=None,
+                   metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                   help="write profiles/hbm_traffic.json from rocprofv3 counter CSVs of this benchmark and of "
+                        "--copy-calibration 1024 (no GPU needed)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     return p.parse_args()
@@ -70,6 +74,58 @@ def copy_calibration(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_mib": mib, "bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}))
+
+
+def traffic_summary(fetch_csv, write_csv, cfetch_csv, cwrite_csv, prec, n, batch):
+    """Writes profiles/hbm_traffic.json from rocprofv3 --pmc FETCH_SIZE and
+    WRITE_SIZE runs of this benchmark (one dispatch per kernel: the one with the
+    most traffic) and of --copy-calibration (a plain copy of known size, whose
+    readings give the counters' byte scale); prints the table rows."""
+    import csv
+    import re
+
+    def per_kernel(path, counter):
+        best = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            k, v = r["Kernel_Name"], float(r["Counter_Value"])
+            best[k] = max(best.get(k, 0.0), v)
+        return best
+
+    cf, cw = per_kernel(cfetch_csv, "FETCH_SIZE"), per_kernel(cwrite_csv, "WRITE_SIZE")
+    copy_f = max(v for k, v in cf.items() if "copyBuffer" in k or "elementwise" in k or "copy" in k.lower())
+    copy_w = max(v for k, v in cw.items() if "copyBuffer" in k or "elementwise" in k or "copy" in k.lower())
+    mib = 1024  # the calibration copy: --copy-calibration 1024
+    fetch_scale = mib * 1024.0 / copy_f   # counters in KiB
+    write_scale = mib * 1024.0 / copy_w
+    fe, wr = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    entries = {}
+    rows = []
+    for k in sorted(fe):
+        m = re.search(r"k_(potrf|trsyl|trlyap)_(f64|large|mixed|single)|k_jacobi_mixed<\d+, \d+, (true|false)>", k)
+        if not m:
+            continue
+        if m.group(1):
+            op = m.group(1)
+            kp = prec if m.group(2) == "mixed" else "f64"
+        else:
+            op = "trlyap" if m.group(3) == "true" else "trsyl"
+            kp = prec
+        fb = fe[k] * 1024.0 * fetch_scale
+        wb = wr.get(k, 0.0) * 1024.0 * write_scale
+        key = f"{op}/{kp}/n{n}/b{batch}"
+        alg = batch * min_bytes(op, n)
+        rows.append(f"| `{k}` | {fe[k]:.0f} | {wr.get(k, 0.0):.0f} | {fb / 1e6:.1f} MB | {wb / 1e6:.1f} MB | "
+                    f"{alg / 1e6:.1f} MB | {(fb + wb) / alg:.2f} |")
+        if key not in entries or fb + wb > entries[key]["fetch_bytes"] + entries[key]["write_bytes"]:
+            entries[key] = {"kernel": k, "fetch_bytes": fb, "write_bytes": wb}
+    out = {"lib_hash": lib_hash(), "source": "profiles/hbm_traffic_n64.md", "fetch_scale": fetch_scale,
+           "write_scale": write_scale, "entries": entries}
+    json.dump(out, open(os.path.join(ROOT, "profiles", "hbm_traffic.json"), "w"), indent=1)
+    print(f"calibration: copy of {mib} MiB reads FETCH_SIZE {copy_f:.0f} KiB, WRITE_SIZE {copy_w:.0f} KiB; "
+          f"scales {fetch_scale:.3f} (reads), {write_scale:.3f} (writes)")
+    print("\n".join(rows))
 
 
 def flops(op, n):
@@ -269,6 +325,9 @@ def main():
     a = parse()
     if a.copy_calibration:
         copy_calibration(a.copy_calibration)
+        return
+    if a.traffic_summary:
+        traffic_summary(*a.traffic_summary, a.prec, a.n, a.batch)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a design "
