@@ -305,10 +305,12 @@ def lib_hash():
     return hashlib.sha256(open(tla.LIB_PATH, "rb").read()).hexdigest()[:16]
 
 
-def traffic_for(kernel_op, prec, n, batch):
+def traffic_for(kernel_op, prec, n, batch, splitting=None):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or
-    None when the summary is missing or the library has changed since."""
+    None when the summary is missing, the library has changed since, or the
+    summary's kernel is not the one this run's plan launches (splitting: the
+    plan is the splitting-iteration solve, k_jacobi_mixed)."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         d = json.load(open(path))
@@ -317,6 +319,8 @@ def traffic_for(kernel_op, prec, n, batch):
     key = f"{kernel_op}/{prec}/n{n}/b{batch}"
     e = d.get("entries", {}).get(key)
     if not e or d.get("lib_hash") != lib_hash():
+        return None
+    if splitting is not None and ("jacobi" in e.get("kernel", "")) != splitting:
         return None
     return e["fetch_bytes"] + e["write_bytes"]
 
@@ -389,8 +393,10 @@ def main():
     # roofline of the dominant kernel: algorithmic bytes per launch / its mean launch time
     dom = max(kern, key=kern.get)
     ach = batch * min_bytes(dom, n) / kern[dom] / 1e9
+    dom_plan = h.get_plan(dom, n, a.prec, batch)
+    splitting = a.prec != "f64" and tla.variant_name(dom, dom_plan.variant) == "jacobi-sweeps"
     res["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(dom, a.prec, n, batch),
+                       "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(dom, a.prec, n, batch, splitting),
                        "algorithmic_bytes": batch * min_bytes(dom, n),
                        "fp64_tflops": batch * flops(dom, n) / kern[dom] / 1e12}
     res["plans"] = {op: list(h.get_plan(op, n, a.prec, batch).astuple()) for op in ops}
