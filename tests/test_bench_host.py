@@ -43,6 +43,13 @@ def test_traffic_lookup_requires_the_same_library(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "lib_hash", lambda: "abc")
     assert bench.traffic_for("trsyl", "mixed_f32", 64, 8192) == 7.0
     assert bench.traffic_for("trsyl", "mixed_f32", 64, 4096) is None
+    # the summary's kernel must be the one the run's plan launches
+    assert bench.traffic_for("trsyl", "mixed_f32", 64, 8192, splitting=False) == 7.0
+    assert bench.traffic_for("trsyl", "mixed_f32", 64, 8192, splitting=True) is None
+    entry["trsyl/mixed_f32/n64/b8192"]["kernel"] = "tla::k_jacobi_mixed<4, 1, false>"
+    (prof / "hbm_traffic.json").write_text(json.dumps({"lib_hash": "abc", "entries": entry}))
+    assert bench.traffic_for("trsyl", "mixed_f32", 64, 8192, splitting=True) == 7.0
+    assert bench.traffic_for("trsyl", "mixed_f32", 64, 8192, splitting=False) is None
     monkeypatch.setattr(bench, "lib_hash", lambda: "other")
     assert bench.traffic_for("trsyl", "mixed_f32", 64, 8192) is None
 
