@@ -47,7 +47,7 @@ def parse():
                    help="wall time of the all-threads oracle run (whole passes over the step's instances)")
     p.add_argument("--ops", default="potrf,trsyl,trlyap")
     p.add_argument("--workload", default="headline",
-                   choices=["headline", "potrf16", "sweep", "ragged", "large", "planner", "potrs", "variants", "plan", "exact", "general"],
+                   choices=["headline", "potrf16", "sweep", "ragged", "large", "planner", "potrs", "variants", "plan", "exact", "general", "peaks"],
                    help="headline: the metric's configuration (default); the others print their own lines")
     p.add_argument("--plan", default=None, metavar="V,T,E,W,P",
                    help="--workload plan: time this plan (variant,tile,engine,waves,place) for the first of --ops")

@@ -1,5 +1,5 @@
 """The benchmark's secondary workloads (one JSON line each), run with
-python bench.py --workload {potrf16,sweep,ragged,large,planner,potrs,variants,plan,exact,general}.
+python bench.py --workload {potrf16,sweep,ragged,large,planner,potrs,variants,plan,exact,general,peaks}.
 
 potrf16 : FP64 Cholesky, 1024 instances at n = 16, replayed many times inside
           one HIP graph (the batch is too small to fill the GPU by itself).
@@ -17,6 +17,8 @@ variants: best time of each blocked-algorithm variant (over tiles, engines,
           n = 128, 256 above (one in-place plan per variant there).
 exact   : exact-size kernels (compiled at run time for each n) against the
           ahead-of-time kernels of the same plan, FP64, n = 4..128.
+peaks   : re-measured HBM and FP64 product ceilings, and the cold / hot regimes of
+          FP64 trsyl at n = 64.
 general : general Sylvester and Lyapunov equations through the Schur front
           end (Schur forms, transforms, triangular solve), FP64 and mixed,
           n = 16, 32, 64, 8192 instances.
@@ -501,6 +503,92 @@ def general(a):
     h.close()
 
 
+def peaks(a):
+    """Re-measured ceilings of this GPU and the cold / hot regimes of the
+    headline Sylvester solve: HBM streaming rates (device copy, read-only
+    reduction), the library's batched FP64 product rate, and FP64 trsyl at
+    n = 64 with inputs rotating through sets larger than the caches (cold)
+    versus a small batch re-solved in the same buffers (hot)."""
+    import torch
+    import paper_1906_08613_amd as tla
+    from paper_1906_08613_amd import inputs as I
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = _events(torch)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return float(np.median(ts))
+
+    nbytes = 4 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    t = timed(lambda: dst.copy_(src))
+    copy_gbs = 2 * nbytes / t / 1e9
+    t = timed(lambda: src.sum())
+    read_gbs = nbytes / t / 1e9
+    del src, dst
+    A = torch.randn(64, 1024, 1024, dtype=torch.float64, device="cuda")
+    B = torch.randn(64, 1024, 1024, dtype=torch.float64, device="cuda")
+    t = timed(lambda: torch.bmm(A, B))
+    gemm_tfs = 2 * 64 * 1024 ** 3 / t / 1e12
+    del A, B
+    print(json.dumps({"workload": "peaks", "hbm_copy_gbs": copy_gbs, "hbm_read_gbs": read_gbs,
+                      "hbm_datasheet_gbs": 8000.0, "fp64_library_gemm_tfs": gemm_tfs,
+                      "fp64_datasheet_tfs": 78.6}), flush=True)
+
+    # cold / hot: FP64 trsyl, n = 64, in place on C (restored outside the timed region)
+    h = tla.Handle(0)
+    n = 64
+
+    def setup(batch, tag):
+        L, U, C = I.trsyl_problem(tag, n, batch)
+        dev = [tla.to_device_cm(L), tla.to_device_cm(U), tla.to_device_cm(C)]
+        return dev, dev[2].clone(), tla.Operands(n, *dev)
+
+    def launch(dev, ops):
+        h.trsyl_batched("f64", ops.batch, n, ops.n, ops.ptrs[0], ops.lds[0], ops.ptrs[1], ops.lds[1],
+                        ops.ptrs[2], ops.lds[2], ops.info, ops.stat)
+
+    def per_instance(sets, reps):
+        ts = []
+        for r in range(reps):
+            dev, pristine, ops = sets[r % len(sets)]
+            dev[2].copy_(pristine)
+            torch.cuda.synchronize()
+            e0, e1 = _events(torch)
+            e0.record()
+            launch(dev, ops)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3 / ops.batch)
+        return float(np.median(ts[1:]))
+
+    cold_sets = [setup(8192, f"cold{k}") for k in range(4)]   # 4 x 0.8 GB of operands
+    cold = per_instance(cold_sets, 9)
+    del cold_sets
+    # hot: a batch whose operands fit the 256 MB MALL (2048 x 99 KB), re-solved
+    # in the same buffers; it fills only part of the GPU (five resident
+    # instances per SIMD need 5120), so its per-instance time also carries the
+    # lower occupancy
+    hot_set = [setup(2048, "hot")]
+    hot = per_instance(hot_set, 9)
+    cold_small = [setup(2048, f"coldsmall{k}") for k in range(8)]  # 8 x 200 MB rotating
+    cold2 = per_instance(cold_small, 9)
+    by = (n * (n + 1) + 2 * n * n) * 8
+    print(json.dumps({"workload": "trsyl f64 n=64: cold (rotating sets larger than the caches) vs hot (same buffers)",
+                      "cold_8192_us_per_instance": cold * 1e6, "cold_8192_gbs": by / cold / 1e9,
+                      "cold_2048_us_per_instance": cold2 * 1e6, "hot_2048_us_per_instance": hot * 1e6,
+                      "cold_2048_gbs": by / cold2 / 1e9, "hot_2048_gbs": by / hot / 1e9}), flush=True)
+    h.close()
+
+
 def potrs(a):
     import torch
     import oracle
@@ -585,4 +673,5 @@ def variants(a):
 
 def run(a):
     {"potrf16": potrf16, "sweep": sweep, "ragged": ragged, "large": large, "planner": planner,
-     "potrs": potrs, "variants": variants, "plan": plan, "exact": exact, "general": general}[a.workload](a)
+     "potrs": potrs, "variants": variants, "plan": plan, "exact": exact, "general": general,
+     "peaks": peaks}[a.workload](a)
