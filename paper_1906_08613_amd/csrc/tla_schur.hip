@@ -424,7 +424,7 @@ k_schur(SchurArgs g) {
 }
 
 // ------------------------------------------------------------ prep
-struct PrepArgs {
+struct GePrepArgs {
   int batch, n_max, nsets;
   const int* n;
   const int* st0;       // status of the first coefficient
@@ -440,7 +440,7 @@ struct PrepArgs {
   long long stride;
 };
 
-__global__ void k_ge_prep(PrepArgs g) {
+__global__ void k_ge_prep(GePrepArgs g) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= g.batch) return;
   int st = g.st0[b];
@@ -642,7 +642,7 @@ tla_status ge_solve(tla_ctx* h, int op, tla_prec prec, int batch, int n_max, con
   else hipLaunchKernelGGL(k_schur<64>, sg, dim3(64), 0, h->stream, sa);
   GE_HIP(hipGetLastError());
 
-  PrepArgs pa{};
+  GePrepArgs pa{};
   pa.batch = batch;
   pa.n_max = nm;
   pa.n = n;
