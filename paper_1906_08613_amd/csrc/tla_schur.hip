@@ -54,6 +54,7 @@ struct SchurSet {
   double* t;               // triangular factor: instance b at t + b * stride, leading dimension n_max
   double* q;               // Schur vectors (M or M^T = Q T Q^T), same layout
   int* status;             // int[batch]
+  int* esc;                // int[batch]: T was formed scaled by 2^-esc[b]
 };
 
 struct SchurArgs {
@@ -93,38 +94,56 @@ TLA_DI void givens(double x, double y, double& c, double& s) {
   s = ys / r;
 }
 
-// The same rotation without divisions: 1 / sqrt(x^2 + y^2) from the hardware
-// estimate refined by two Newton steps; the scaled form above where
-// x^2 + y^2 could overflow or lose precision to underflow.
-TLA_DI void givens_fast(double x, double y, double& c, double& s) {
-  const double r2 = x * x + y * y;
-  if (!(r2 > 1e-280 && r2 < 1e280)) {
-    givens(x, y, c, s);
-    return;
-  }
+// c a + s b and c b - s a, each rounded the same way wherever it is formed:
+// the bulge chase keeps a copy of the entries it needs next in every lane and
+// must reproduce the stored values bit for bit.
+TLA_DI double rot_hi(double c, double s, double a, double b) { return __builtin_fma(c, a, s * b); }
+TLA_DI double rot_lo(double c, double s, double a, double b) { return __builtin_fma(c, b, -(s * a)); }
+
+// The rotation of the bulge chase without divisions or branches: 1 / sqrt(x^2
+// + y^2) from the hardware estimate refined by two Newton steps, the second
+// folded into the products x / r and y / r.  The matrix is scaled at ingest so
+// that its largest entry lies in [1/2, 1): x^2 + y^2 cannot overflow, and a
+// pair below 2^-500 (far under the working precision of such a matrix) gets
+// the identity.
+TLA_DI void givens_chase(double x, double y, double& c, double& s) {
+  const double r2 = __builtin_fma(x, x, y * y);
+  const double r2h = 0.5 * r2;  // the halves of the Newton steps, exact
   double ri = __builtin_amdgcn_rsq(r2);
-  ri = __builtin_fma(0.5 * ri, __builtin_fma(-r2 * ri, ri, 1.0), ri);
-  ri = __builtin_fma(0.5 * ri, __builtin_fma(-r2 * ri, ri, 1.0), ri);
-  c = x * ri;
-  s = y * ri;
+  ri = __builtin_fma(ri, __builtin_fma(-r2h * ri, ri, 0.5), ri);
+  const double h = __builtin_fma(-r2h * ri, ri, 0.5);
+  const double cx = x * ri, sy = y * ri;
+  const bool ok = r2 >= 0x1p-1000;
+  c = ok ? __builtin_fma(cx, h, cx) : 1.0;
+  s = ok ? __builtin_fma(sy, h, sy) : 0.0;
 }
 
-// Rotation of rows (k, k+1) over columns j0..n-1 and of columns (k, k+1)
-// over rows 0..i1 of H (LDS, leading dimension LD), as the similarity
-// H <- G^T H G with G = [[c, -s], [s, c]] in the plane (k, k+1).
-template <int LD>
-TLA_DI void rotate_h(lds_t<double>* H, int n, int k, int j0, int i1, double c, double s) {
+TLA_DI double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return uni(v);
+}
+
+// Column j of the Hessenberg matrix during the bulge chase has its nonzeros
+// in rows 0..j+1 and the bulge in row j+2: stored packed by columns, rows
+// 0..j+2 of column j at pk(0, j) + i.
+TLA_DI int pk(int i, int j) { return ((j * (j + 5)) >> 1) + i; }
+
+// Rotation of rows (k, k+1) over columns k..n-1 and of columns (k, k+1) over
+// rows 0..k+1 of the packed H, as the similarity H <- G^T H G with
+// G = [[c, -s], [s, c]] in the plane (k, k+1) (the split of a 2 x 2 block).
+TLA_DI void rotate_pk(lds_t<double>* H, int n, int k, double c, double s) {
   const int l = lane_id();
-  if (l >= j0 && l < n) {
-    const double a = H[k + l * LD], b = H[k + 1 + l * LD];
-    H[k + l * LD] = c * a + s * b;
-    H[k + 1 + l * LD] = c * b - s * a;
+  if (l >= k && l < n) {
+    const double a = H[pk(k, l)], b = H[pk(k + 1, l)];
+    H[pk(k, l)] = c * a + s * b;
+    H[pk(k + 1, l)] = c * b - s * a;
   }
   compiler_fence();
-  if (l <= i1) {
-    const double a = H[l + k * LD], b = H[l + (k + 1) * LD];
-    H[l + k * LD] = c * a + s * b;
-    H[l + (k + 1) * LD] = c * b - s * a;
+  if (l <= k + 1) {
+    const double a = H[pk(l, k)], b = H[pk(l, k + 1)];
+    H[pk(l, k)] = c * a + s * b;
+    H[pk(l, k + 1)] = c * b - s * a;
   }
   compiler_fence();
 }
@@ -174,18 +193,20 @@ TLA_DI void reset_rotations(lds_t<double>* cs, int lo, int hi) {
 
 }  // namespace
 
-// NM: largest order handled (16, 32 or 64): the LDS holds H (NM x (NM + 1)),
-// each lane holds one row of Q (NM registers).
+// ------------------------------------------------------------ Hessenberg
+// NM: largest order handled (16, 32 or 64).  One wave per matrix: the LDS
+// holds the dense matrix (NM x (NM + 1)), each lane one row of Q (NM
+// registers).  Output: H = Q^T M Q (upper Hessenberg, exact zeros below the
+// subdiagonal, scaled by 2^-esc) in the T slot, Q in the Q slot, esc, and the
+// status (0, or the argument / non-finite code that ends the instance).
 template <int NM>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM == 64 ? 1 : (NM == 32 ? 2 : 3)))) void
-k_schur(SchurArgs g) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM == 64 ? 1 : (NM == 32 ? 4 : 5)))) void
+k_hess(SchurArgs g) {
   constexpr int LD = NM + 1;  // odd: row and column walks spread over the banks
   __shared__ double Hs[NM * LD];
   __shared__ double vs_s[64];
-  __shared__ double cs_s[2 * NM];
   lds_t<double>* H = to_lds(Hs);
   lds_t<double>* vs = to_lds(vs_s);
-  lds_t<double>* cs = to_lds(cs_s);
   const int si = blockIdx.x / g.batch, b = blockIdx.x - si * g.batch;
   const SchurSet S = g.set[si];
   const int l = lane_id();
@@ -206,10 +227,12 @@ k_schur(SchurArgs g) {
   // ---- ingest: column j of M is read by the lanes (coalesced); M^T is stored transposed
   const gbl_t<double>* M = to_gbl(S.m[b]);
   bool finite = true;
+  double amax = 0.0;
   for (int j = 0; j < n; ++j) {
     if (l < n) {
       const double v = M[l + (size_t)j * ldm];
       finite = finite && __builtin_isfinite(v);
+      amax = fmax(amax, fabs(v));
       if (S.trans) H[j + l * LD] = v;
       else H[l + j * LD] = v;
     }
@@ -218,10 +241,14 @@ k_schur(SchurArgs g) {
     if (l == 0) S.status[b] = kGeNoConv;
     return;
   }
-  if (l < NM) {
-    cs[2 * l] = 1.0;
-    cs[2 * l + 1] = 0.0;
-  }
+  // scale by a power of two (exact) so that the largest entry lies in [1/2, 1);
+  // T is scaled back at the end, the Schur vectors do not depend on it
+  int esc = 0;
+  amax = wave_max(amax);
+  if (amax > 0.0) frexp(amax, &esc);
+  compiler_fence();
+  if (esc != 0 && l < n)
+    for (int j = 0; j < n; ++j) H[l + j * LD] = ldexp(H[l + j * LD], -esc);
   compiler_fence();
 
   double q[NM];
@@ -240,30 +267,111 @@ k_schur(SchurArgs g) {
     const double sc = 1.0 / (alpha - beta);
     vs[l] = l == k + 1 ? 1.0 : (l > k + 1 ? xi * sc : 0.0);
     compiler_fence();
-    // left: rows k+1..n-1 of columns k+1..n-1 (lane = column)
+    // left: rows k+1..n-1 of columns k+1..n-1 (lane = column); the dot
+    // products below run as four interleaved partial sums
     if (l > k && l < n) {
-      double w = 0.0;
-      for (int i = k + 1; i < n; ++i) w += vs[i] * H[i + l * LD];
-      w *= tau;
-      for (int i = k + 1; i < n; ++i) H[i + l * LD] -= vs[i] * w;
+      double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+      int i = k + 1;
+      for (; i + 3 < n; i += 4) {
+        w0 += vs[i] * H[i + l * LD];
+        w1 += vs[i + 1] * H[i + 1 + l * LD];
+        w2 += vs[i + 2] * H[i + 2 + l * LD];
+        w3 += vs[i + 3] * H[i + 3 + l * LD];
+      }
+      for (; i < n; ++i) w0 += vs[i] * H[i + l * LD];
+      const double w = tau * ((w0 + w1) + (w2 + w3));
+      for (i = k + 1; i < n; ++i) H[i + l * LD] -= vs[i] * w;
       H[l + k * LD] = l == k + 1 ? beta : 0.0;
     }
     compiler_fence();
     // right: columns k+1..n-1 of every row (lane = row)
     if (l < n) {
-      double u = 0.0;
-      for (int j = k + 1; j < n; ++j) u += H[l + j * LD] * vs[j];
-      u *= tau;
-      for (int j = k + 1; j < n; ++j) H[l + j * LD] -= u * vs[j];
+      double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+      int j = k + 1;
+      for (; j + 3 < n; j += 4) {
+        u0 += H[l + j * LD] * vs[j];
+        u1 += H[l + (j + 1) * LD] * vs[j + 1];
+        u2 += H[l + (j + 2) * LD] * vs[j + 2];
+        u3 += H[l + (j + 3) * LD] * vs[j + 3];
+      }
+      for (; j < n; ++j) u0 += H[l + j * LD] * vs[j];
+      const double u = tau * ((u0 + u1) + (u2 + u3));
+      for (j = k + 1; j < n; ++j) H[l + j * LD] -= u * vs[j];
     }
-    double u = 0.0;
+    double uq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < NM; ++j) u += q[j] * vs[j];
-    u *= tau;
+    for (int j = 0; j < NM; ++j) {
+      uq[j & 3] += q[j] * vs[j];
+      if ((j & 15) == 15) compiler_fence();  // a bounded number of v loads in flight
+    }
+    const double u = tau * ((uq[0] + uq[1]) + (uq[2] + uq[3]));
 #pragma unroll
-    for (int j = 0; j < NM; ++j) q[j] -= u * vs[j];
+    for (int j = 0; j < NM; ++j) {
+      q[j] -= u * vs[j];
+      if ((j & 15) == 15) compiler_fence();
+    }
     compiler_fence();
   }
+  // ---- hand-off to the QR kernel through the output slots
+  gbl_t<double>* T = to_gbl(S.t + (size_t)b * g.stride);
+  gbl_t<double>* Q = to_gbl(S.q + (size_t)b * g.stride);
+  const int ld = g.n_max;
+  for (int j = 0; j < n; ++j)
+    if (l < n) T[l + (size_t)j * ld] = H[l + j * LD];
+#pragma unroll
+  for (int j = 0; j < NM; ++j)
+    if (j < n && l < n) Q[l + (size_t)j * ld] = q[j];
+  if (l == 0) {
+    S.esc[b] = esc;
+    S.status[b] = 0;
+  }
+}
+
+// ------------------------------------------------------------ QR iteration
+// NM: largest order handled (16, 32 or 64).  One wave per matrix, the packed
+// Hessenberg matrix in LDS (NM (NM + 5) / 2 doubles: two waves per SIMD at
+// NM = 64), each lane one row of Q in registers.  Takes the Hessenberg kernel's
+// output from the T and Q slots and leaves T (or T^T) and Q there.
+template <int NM>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM == 64 ? 2 : (NM == 32 ? 3 : 4)))) void
+k_schur_qr(SchurArgs g) {
+  constexpr int PS = NM * (NM + 5) / 2;
+  __shared__ double Hs[PS];
+  __shared__ double cs_s[2 * NM];
+  __shared__ double junk_s[2 * 64 + 2];  // target of the stores of lanes outside a rotation's range
+  lds_t<double>* H = to_lds(Hs);
+  lds_t<double>* cs = to_lds(cs_s);
+  lds_t<double>* J = to_lds(junk_s);
+  const int si = blockIdx.x / g.batch, b = blockIdx.x - si * g.batch;
+  const SchurSet S = g.set[si];
+  const int l = lane_id();
+  const int n = g.n[b];
+  if (n < 1 || n > g.n_max || S.status[b] != 0) return;  // ended by the Hessenberg kernel (or empty)
+  gbl_t<double>* T = to_gbl(S.t + (size_t)b * g.stride);
+  gbl_t<double>* Q = to_gbl(S.q + (size_t)b * g.stride);
+  const int ld = g.n_max;
+  const int esc = S.esc[b];
+  // ---- ingest: the Hessenberg part of column j (lane = row), a zero bulge slot below it
+  for (int j = 0; j < n; ++j) {
+    if (l <= j + 1 && l < n) H[pk(l, j)] = T[l + (size_t)j * ld];
+    else if (l <= j + 2) H[pk(l, j)] = 0.0;
+  }
+  // rows and columns past n are read clamped (in the slot, never used nor stored)
+  double q[NM];
+  {
+    const gbl_t<double>* Qp = Q + (l < n ? l : n - 1);
+#pragma unroll
+    for (int j = 0; j < NM; ++j) {
+      q[j] = *Qp;
+      if (j + 1 < n) Qp += ld;
+      if ((j & 7) == 7) compiler_fence();  // eight loads in flight at a time
+    }
+  }
+  if (l < NM) {
+    cs[2 * l] = 1.0;
+    cs[2 * l + 1] = 0.0;
+  }
+  compiler_fence();
 
   // ---- implicit single-shift QR on the active window [lo, hi]
   const double ulp = 2.220446049250313e-16;           // 2^-52
@@ -274,27 +382,26 @@ k_schur(SchurArgs g) {
     // diagonal neighbours
     bool neg = false;
     if (l >= 1 && l <= hi) {
-      const double sub = fabs(H[l + (l - 1) * LD]);
-      double tst = fabs(H[(l - 1) + (l - 1) * LD]) + fabs(H[l + l * LD]);
+      const double sub = fabs(H[pk(l, l - 1)]);
+      double tst = fabs(H[pk(l - 1, l - 1)]) + fabs(H[pk(l, l)]);
       if (tst == 0.0) {
-        if (l >= 2) tst += fabs(H[(l - 1) + (l - 2) * LD]);
-        if (l + 1 <= hi) tst += fabs(H[(l + 1) + l * LD]);
+        if (l >= 2) tst += fabs(H[pk(l - 1, l - 2)]);
+        if (l + 1 <= hi) tst += fabs(H[pk(l + 1, l)]);
       }
       neg = sub <= smlnum || sub <= ulp * tst;
     }
     const unsigned long long mask = __ballot(neg);
     const int lo = mask ? 63 - __clzll(mask) : 0;
     compiler_fence();
-    if (lo > 0 && l == 0) H[lo + (lo - 1) * LD] = 0.0;
+    if (lo > 0 && l == 0) H[pk(lo, lo - 1)] = 0.0;
     compiler_fence();
+    int rlo = 0, rhi = 0;  // rotations of this step, recorded in cs at rlo..rhi-1
     if (lo == hi) {  // 1 x 1 block: an eigenvalue
       hi -= 1;
       its = 0;
-      continue;
-    }
-    if (lo == hi - 1) {  // 2 x 2 block: split it if its eigenvalues are real
-      const double a = uni(H[lo + lo * LD]), bq = uni(H[lo + hi * LD]);
-      const double e = uni(H[hi + lo * LD]), d = uni(H[hi + hi * LD]);
+    } else if (lo == hi - 1) {  // 2 x 2 block: split it if its eigenvalues are real
+      const double a = uni(H[pk(lo, lo)]), bq = uni(H[pk(lo, hi)]);
+      const double e = uni(H[pk(hi, lo)]), d = uni(H[pk(hi, hi)]);
       const double p = 0.5 * (a - d), disc = p * p + bq * e;
       if (disc < 0.0) {
         fail = kGeComplex;
@@ -307,120 +414,132 @@ k_schur(SchurArgs g) {
         double c, s;
         givens(z, e, c, s);
         compiler_fence();
-        rotate_h<LD>(H, n, lo, lo, hi, c, s);
+        rotate_pk(H, n, lo, c, s);
         if (l == 0) {
           cs[2 * lo] = c;
           cs[2 * lo + 1] = s;
-          H[hi + lo * LD] = 0.0;
+          H[pk(hi, lo)] = 0.0;
         }
-        compiler_fence();
-        rotate_q<NM>(q, cs, lo, lo + 1);
-        compiler_fence();
-        reset_rotations(cs, lo, lo + 1);
+        rlo = lo;
+        rhi = lo + 1;
       }
       hi -= 2;
       its = 0;
-      continue;
-    }
-    if (++its > kSchurMaxIts) {
-      // no deflation: a complex pair at the bottom of the window, or no convergence
-      const double a = uni(H[(hi - 1) + (hi - 1) * LD]), bq = uni(H[(hi - 1) + hi * LD]);
-      const double e = uni(H[hi + (hi - 1) * LD]), d = uni(H[hi + hi * LD]);
-      const double p = 0.5 * (a - d);
-      fail = p * p + bq * e < 0.0 ? kGeComplex : kGeNoConv;
-      break;
-    }
-    // shift: the eigenvalue of the trailing 2 x 2 block nearer its last
-    // diagonal entry (Wilkinson), its last diagonal entry when that block has
-    // complex eigenvalues, and an ad hoc exceptional shift every 10th step
-    const double a = uni(H[(hi - 1) + (hi - 1) * LD]), bq = uni(H[(hi - 1) + hi * LD]);
-    const double e = uni(H[hi + (hi - 1) * LD]), d = uni(H[hi + hi * LD]);
-    double sigma;
-    if (its % 10 == 0) {
-      sigma = d + 0.75 * fabs(e);
     } else {
-      const double p = 0.5 * (a - d), disc = p * p + bq * e;
-      sigma = d;
-      if (disc >= 0.0) {
-        const double z = p + copysign(sqrt(disc), p);
-        if (z != 0.0) sigma = d - bq * e / z;
+      if (++its > kSchurMaxIts) {
+        // no deflation: a complex pair at the bottom of the window, or no convergence
+        const double a = uni(H[pk(hi - 1, hi - 1)]), bq = uni(H[pk(hi - 1, hi)]);
+        const double e = uni(H[pk(hi, hi - 1)]), d = uni(H[pk(hi, hi)]);
+        const double p = 0.5 * (a - d);
+        fail = p * p + bq * e < 0.0 ? kGeComplex : kGeNoConv;
+        break;
       }
-    }
-    // the sweep: the first rotation from the shifted first column, then the
-    // bulge chased down the window.  Rotation k updates rows (k, k+1) (lane =
-    // column) and then columns (k, k+1) (lane = row).  Both operand pairs are
-    // read before either update: the row update changes no column operand
-    // except those of rows k and k+1, which lanes k and k+1 take from the row
-    // update's results (cross-lane reads), and the next rotation's pair
-    // (h_{k+1,k}, h_{k+2,k}) comes from the column update's results the same
-    // way; the LDS then carries only the stores, and the loads of the next
-    // rotation overlap the computation of its (c, s).
-    double x = uni(H[lo + lo * LD]) - sigma, y = uni(H[(lo + 1) + lo * LD]);
-    compiler_fence();
-    for (int k = lo; k < hi; ++k) {
-      const int j0 = k > lo ? k - 1 : lo;
-      const int i1 = k + 2 < hi ? k + 2 : hi;
-      const bool rl = l >= j0 && l < n, cl = l <= i1;
-      const int lr = l < n ? l : n - 1;
-      const double ra = H[k + lr * LD], rb = H[(k + 1) + lr * LD];
-      double ca = H[lr + k * LD], cb = H[lr + (k + 1) * LD];
+      // shift: the eigenvalue of the trailing 2 x 2 block nearer its last
+      // diagonal entry (Wilkinson), its last diagonal entry when that block has
+      // complex eigenvalues, and an ad hoc exceptional shift every 10th step
+      const double a = uni(H[pk(hi - 1, hi - 1)]), bq = uni(H[pk(hi - 1, hi)]);
+      const double e = uni(H[pk(hi, hi - 1)]), d = uni(H[pk(hi, hi)]);
+      double sigma;
+      if (its % 10 == 0) {
+        sigma = d + 0.75 * fabs(e);
+      } else {
+        const double p = 0.5 * (a - d), disc = p * p + bq * e;
+        sigma = d;
+        if (disc >= 0.0) {
+          const double z = p + copysign(sqrt(disc), p);
+          if (z != 0.0) sigma = d - bq * e / z;
+        }
+      }
+      // the sweep: the first rotation from the shifted first column, then the
+      // bulge chased down the window.  Rotation k turns rows (k, k+1) (lane =
+      // column, columns j0..n-1) and then columns (k, k+1) (lane = row, rows
+      // 0..i1).  Every lane also carries the entries the chain needs next: the
+      // 2 x 2 window H[k..k+1, k..k+1] and H[k+2, k+1] before rotation k, from
+      // which the pair (h_{k+1,k}, h_{k+2,k}) of rotation k+1 follows with the
+      // operations the updating lanes apply (so the copies equal the stored
+      // entries, up to the sign of a zero).  The rotation of step k+1 is thus
+      // formed while the lanes update the matrix for step k, and the LDS carries
+      // no value of the chain.  Lanes outside a rotation's range store into J
+      // instead of being masked, which keeps the step one straight block of code.
+      const int lr = l < NM ? l : NM - 1;
       double c, s;
-      givens_fast(x, y, c, s);
-      const double ra2 = c * ra + s * rb;
-      double rb2 = c * rb - s * ra;
-      if (k > lo && l == k - 1) rb2 = 0.0;  // the annihilated bulge
-      if (rl) {
-        H[k + l * LD] = ra2;
-        H[(k + 1) + l * LD] = rb2;
-      }
-      const double h00 = read_lane(ra2, k), h01 = read_lane(ra2, k + 1);
-      const double h10 = read_lane(rb2, k), h11 = read_lane(rb2, k + 1);
-      if (l == k) {
-        ca = h00;
-        cb = h01;
-      } else if (l == k + 1) {
-        ca = h10;
-        cb = h11;
-      }
-      const double ca2 = c * ca + s * cb, cb2 = c * cb - s * ca;
-      if (cl) {
-        H[l + k * LD] = ca2;
-        H[l + (k + 1) * LD] = cb2;
-      }
-      if (l == 0) {
-        cs[2 * k] = c;
-        cs[2 * k + 1] = s;
-      }
-      if (k + 1 < hi) {
-        x = read_lane(ca2, k + 1);
-        y = read_lane(ca2, k + 2);
-      }
+      givens_chase(uni(H[pk(lo, lo)]) - sigma, uni(H[pk(lo + 1, lo)]), c, s);
+      double wa = uni(H[pk(lo, lo)]), wb = uni(H[pk(lo, lo + 1)]);
+      double wd = uni(H[pk(lo + 1, lo)]), we = uni(H[pk(lo + 1, lo + 1)]);
+      double wf = uni(H[pk(lo + 2, lo + 1)]);  // lo + 2 <= hi: the window has three rows at least
       compiler_fence();
+#pragma unroll 2
+      for (int k = lo; k < hi; ++k) {
+        const int j0 = k > lo ? k - 1 : lo;
+        const int i1 = k + 2 < hi ? k + 2 : hi;
+        // rows k, k+1 of this lane's column (outside the packed column for
+        // lanes left of j0: read, never stored), and column k+2 rows k..k+3 (the
+        // window of rotation k+1; clamped into H on the last step, unused there)
+        const lds_t<double>* rp = H + pk(k, lr);
+        const double ra = rp[0], rb = rp[1];
+        const int wo = min(pk(k, k + 2), PS - 4);
+        const double g0 = H[wo], g1 = H[wo + 1], g2 = H[wo + 2], g3 = H[wo + 3];
+        // the chain: rotation k on the window, then rotation k+1
+        const double d1 = rot_lo(c, s, wa, wd), e1 = rot_lo(c, s, wb, we);
+        const double xn = rot_hi(c, s, d1, e1), an = rot_lo(c, s, d1, e1);
+        const double yn = s * wf, dn = c * wf;
+        double cn, sn;
+        givens_chase(xn, yn, cn, sn);
+        // rows k, k+1; the bulge h_{k+1,k-1} is annihilated exactly
+        const double ra2 = rot_hi(c, s, ra, rb);
+        const double rb2 = l == k - 1 ? 0.0 : rot_lo(c, s, ra, rb);
+        lds_t<double>* rw = (l >= j0 && l < n) ? H + pk(k, l) : J + 2 * l;
+        rw[0] = ra2;
+        rw[1] = rb2;
+        // columns k, k+1 (k + 3 apart in the packed layout), read after the row update
+        const lds_t<double>* cp = H + pk(lr, k);
+        const double ca = cp[0], cb = cp[k + 3];
+        lds_t<double>* cw = l <= i1 ? H + pk(l, k) : J + l;
+        cw[0] = rot_hi(c, s, ca, cb);
+        cw[k + 3] = rot_lo(c, s, ca, cb);
+        lds_t<double>* sw = l == 0 ? cs + 2 * k : J + 2 * l;
+        sw[0] = c;
+        sw[1] = s;
+        // the window of rotation k+1
+        wb = rot_lo(c, s, g0, g1);
+        wa = an;
+        wd = dn;
+        we = g2;
+        wf = g3;
+        c = cn;
+        s = sn;
+      }
+      rlo = lo;
+      rhi = hi;
     }
-    rotate_q<NM>(q, cs, lo, hi);
-    compiler_fence();
-    reset_rotations(cs, lo, hi);
+    // one place applies the step's rotations to the Schur vectors
+    if (rhi > rlo) {
+      compiler_fence();
+      rotate_q<NM>(q, cs, rlo, rhi);
+      compiler_fence();
+      reset_rotations(cs, rlo, rhi);
+    }
   }
   if (fail != 0) {
     if (l == 0) S.status[b] = fail;
     return;
   }
-  // ---- egress: T (or T^T) with exact zeros off its triangle, and Q
-  gbl_t<double>* T = to_gbl(S.t + (size_t)b * g.stride);
-  gbl_t<double>* Q = to_gbl(S.q + (size_t)b * g.stride);
-  const int ld = g.n_max;
+  // ---- egress: T (or T^T) with exact zeros off its triangle, scaled back, and Q
   for (int j = 0; j < n; ++j) {
     if (l < n) {
       double v;
-      if (S.lower) v = l >= j ? H[j + l * LD] : 0.0;
-      else v = l <= j ? H[l + j * LD] : 0.0;
-      T[l + (size_t)j * ld] = v;
+      if (S.lower) v = l >= j ? H[pk(j, l)] : 0.0;
+      else v = l <= j ? H[pk(l, j)] : 0.0;
+      T[l + (size_t)j * ld] = ldexp(v, esc);
     }
   }
+  // in descending order, columns past n-1 clamped onto column n-1: its own
+  // value is stored last (same lane, same address)
+  if (l < n) {
+    gbl_t<double>* Qp = Q + l;
 #pragma unroll
-  for (int j = 0; j < NM; ++j)
-    if (j < n && l < n) Q[l + (size_t)j * ld] = q[j];
-  if (l == 0) S.status[b] = 0;
+    for (int j = NM - 1; j >= 0; --j) Qp[(size_t)(j < n ? j : n - 1) * ld] = q[j];
+  }
 }
 
 // ------------------------------------------------------------ prep
@@ -578,7 +697,7 @@ GeLayout ge_layout(int batch, int n_max, int mats) {
   L.ptr_off = (mat_bytes + 255) & ~(size_t)255;
   const size_t ptr_bytes = (size_t)2 * batch * sizeof(double*);
   L.int_off = (L.ptr_off + ptr_bytes + 255) & ~(size_t)255;
-  L.bytes = L.int_off + (size_t)6 * batch * sizeof(int);
+  L.bytes = L.int_off + (size_t)8 * batch * sizeof(int);
   return L;
 }
 
@@ -627,6 +746,8 @@ tla_status ge_solve(tla_ctx* h, int op, tla_prec prec, int batch, int n_max, con
   int* gstat = ints + 2 * batch;
   int* n_eff = ints + 3 * batch;
   int* ldw = ints + 4 * batch;
+  int* esc0 = ints + 6 * batch;
+  int* esc1 = ints + 7 * batch;
 
   SchurArgs sa{};
   sa.batch = batch;
@@ -634,12 +755,19 @@ tla_status ge_solve(tla_ctx* h, int op, tla_prec prec, int batch, int n_max, con
   sa.nsets = syl ? 2 : 1;
   sa.n = n;
   sa.stride = Lo.stride;
-  sa.set[0] = SchurSet{A, lda, 1, 1, Lt, Zq, st0};
-  if (syl) sa.set[1] = SchurSet{B, ldb, 0, 0, Ut, Wq, st1};
+  sa.set[0] = SchurSet{A, lda, 1, 1, Lt, Zq, st0, esc0};
+  if (syl) sa.set[1] = SchurSet{B, ldb, 0, 0, Ut, Wq, st1, esc1};
   const dim3 sg(batch * sa.nsets);
-  if (nm <= 16) hipLaunchKernelGGL(k_schur<16>, sg, dim3(64), 0, h->stream, sa);
-  else if (nm <= 32) hipLaunchKernelGGL(k_schur<32>, sg, dim3(64), 0, h->stream, sa);
-  else hipLaunchKernelGGL(k_schur<64>, sg, dim3(64), 0, h->stream, sa);
+  if (nm <= 16) {
+    hipLaunchKernelGGL(k_hess<16>, sg, dim3(64), 0, h->stream, sa);
+    hipLaunchKernelGGL(k_schur_qr<16>, sg, dim3(64), 0, h->stream, sa);
+  } else if (nm <= 32) {
+    hipLaunchKernelGGL(k_hess<32>, sg, dim3(64), 0, h->stream, sa);
+    hipLaunchKernelGGL(k_schur_qr<32>, sg, dim3(64), 0, h->stream, sa);
+  } else {
+    hipLaunchKernelGGL(k_hess<64>, sg, dim3(64), 0, h->stream, sa);
+    hipLaunchKernelGGL(k_schur_qr<64>, sg, dim3(64), 0, h->stream, sa);
+  }
   GE_HIP(hipGetLastError());
 
   GePrepArgs pa{};
