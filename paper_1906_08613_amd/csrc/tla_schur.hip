@@ -9,11 +9,14 @@
 //   A X + X B = C   <=>  L Y + Y U = Z^T C W,  X = Z Y W^T
 //   A X + X A^T = S <=>  L Y + Y L^T = Z^T S Z, X = Z Y Z^T
 //
-// Three kernels bracket the existing triangular solves:
-//   k_schur      one wavefront per matrix: Householder reduction to upper
-//                Hessenberg form, then the implicit single-shift QR iteration
-//                (Wilkinson shift, deflation on negligible subdiagonal
-//                entries, exceptional shifts), the Schur vectors accumulated;
+// Four kernels bracket the existing triangular solves:
+//   k_hess       one wavefront per matrix: Householder reduction to upper
+//                Hessenberg form (dense matrix in LDS), the Schur vectors
+//                started;
+//   k_schur_qr   one wavefront per matrix: the implicit single-shift QR
+//                iteration (Wilkinson shift, deflation on negligible
+//                subdiagonal entries, exceptional shifts) on the Hessenberg
+//                matrix packed in LDS, the Schur vectors accumulated;
 //   k_ge_prep    per instance: status merge and the pointer / size arrays the
 //                triangular solves take;
 //   k_ge_xform   one workgroup per matrix: the two-sided transforms
@@ -272,6 +275,7 @@ k_hess(SchurArgs g) {
     if (l > k && l < n) {
       double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
       int i = k + 1;
+#pragma unroll 2
       for (; i + 3 < n; i += 4) {
         w0 += vs[i] * H[i + l * LD];
         w1 += vs[i + 1] * H[i + 1 + l * LD];
@@ -280,6 +284,7 @@ k_hess(SchurArgs g) {
       }
       for (; i < n; ++i) w0 += vs[i] * H[i + l * LD];
       const double w = tau * ((w0 + w1) + (w2 + w3));
+#pragma unroll 8
       for (i = k + 1; i < n; ++i) H[i + l * LD] -= vs[i] * w;
       H[l + k * LD] = l == k + 1 ? beta : 0.0;
     }
@@ -288,6 +293,7 @@ k_hess(SchurArgs g) {
     if (l < n) {
       double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
       int j = k + 1;
+#pragma unroll 2
       for (; j + 3 < n; j += 4) {
         u0 += H[l + j * LD] * vs[j];
         u1 += H[l + (j + 1) * LD] * vs[j + 1];
@@ -296,6 +302,7 @@ k_hess(SchurArgs g) {
       }
       for (; j < n; ++j) u0 += H[l + j * LD] * vs[j];
       const double u = tau * ((u0 + u1) + (u2 + u3));
+#pragma unroll 8
       for (j = k + 1; j < n; ++j) H[l + j * LD] -= u * vs[j];
     }
     double uq[4] = {0.0, 0.0, 0.0, 0.0};
