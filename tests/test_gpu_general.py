@@ -168,6 +168,29 @@ def test_gelyap_uneven_n(h, orc):
         assert rel_err(Xb[None], Xr[None]).max() <= TOL
 
 
+@pytest.mark.parametrize("p", [600, -600])
+def test_power_of_two_scale_invariance(h, p):
+    # A, B, C (and A, S) scaled by 2^p leave X unchanged.  The front end scales
+    # each coefficient by a power of two to entries below 1 before the
+    # Householder and QR steps (whose squares leave the FP64 range at |p| = 600
+    # otherwise), so every step repeats the unscaled one exactly scaled and X
+    # must agree bit for bit
+    n, batch = 33, 3
+    s = np.ldexp(1.0, p)
+    A, B, C = I.gesyl_problem("ge-scale", n, batch)
+    print(f"gesyl scaled 2^{p}", flush=True)
+    X, info = run_gesyl(h, A, B, C)
+    Xs, infos = run_gesyl(h, A * s, B * s, C * s)
+    assert np.all(info == 0) and np.all(infos == 0)
+    assert np.array_equal(Xs, X)
+    A, S = I.gelyap_problem("ge-scale", n, batch)
+    print(f"gelyap scaled 2^{p}", flush=True)
+    X, info = run_gelyap(h, A, S)
+    Xs, infos = run_gelyap(h, A * s, S * s)
+    assert np.all(info == 0) and np.all(infos == 0)
+    assert np.array_equal(Xs, X)
+
+
 def test_complex_eigenvalues_flagged(h, orc):
     # instance 1's A has a complex pair (a rotation block) hidden by an
     # orthogonal similarity; instance 2's B has one; the others still solve
