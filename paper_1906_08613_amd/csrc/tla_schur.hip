@@ -106,19 +106,21 @@ TLA_DI double rot_lo(double c, double s, double a, double b) { return __builtin_
 // The rotation of the bulge chase without divisions or branches: 1 / sqrt(x^2
 // + y^2) from the hardware estimate refined by two Newton steps, the second
 // folded into the products x / r and y / r.  The matrix is scaled at ingest so
-// that its largest entry lies in [1/2, 1): x^2 + y^2 cannot overflow, and a
-// pair below 2^-500 (far under the working precision of such a matrix) gets
-// the identity.
+// that its largest entry lies in [1/2, 1): x^2 + y^2 cannot overflow.  x is
+// first moved by 2^-500 away from zero, which leaves every |x| >= 2^-446
+// unchanged (less than half its last place) and keeps x^2 + y^2 >= 2^-1000:
+// a pair below that (far under the working precision of such a matrix) gets a
+// rotation onto (x', y), the identity for x = y = 0.
 TLA_DI void givens_chase(double x, double y, double& c, double& s) {
-  const double r2 = __builtin_fma(x, x, y * y);
+  const double xe = x + copysign(0x1p-500, x);
+  const double r2 = __builtin_fma(xe, xe, y * y);
   const double r2h = 0.5 * r2;  // the halves of the Newton steps, exact
   double ri = __builtin_amdgcn_rsq(r2);
   ri = __builtin_fma(ri, __builtin_fma(-r2h * ri, ri, 0.5), ri);
   const double h = __builtin_fma(-r2h * ri, ri, 0.5);
-  const double cx = x * ri, sy = y * ri;
-  const bool ok = r2 >= 0x1p-1000;
-  c = ok ? __builtin_fma(cx, h, cx) : 1.0;
-  s = ok ? __builtin_fma(sy, h, sy) : 0.0;
+  const double cx = xe * ri, sy = y * ri;
+  c = __builtin_fma(cx, h, cx);
+  s = __builtin_fma(sy, h, sy);
 }
 
 TLA_DI double wave_max(double v) {
