@@ -199,41 +199,59 @@ TLA_DI void reset_rotations(lds_t<double>* cs, int lo, int hi) {
 }  // namespace
 
 // ------------------------------------------------------------ Hessenberg
-// NM: largest order handled (16, 32 or 64).  One wave per matrix: the LDS
-// holds the dense matrix (NM x (NM + 1)), each lane one row of Q (NM
-// registers).  Output: H = Q^T M Q (upper Hessenberg, exact zeros below the
-// subdiagonal, scaled by 2^-esc) in the T slot, Q in the Q slot, esc, and the
-// status (0, or the argument / non-finite code that ends the instance).
-template <int NM>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM == 64 ? 1 : (NM == 32 ? 4 : 5)))) void
+// NM: largest order handled (16, 32 or 64); NW: waves per matrix (1 or 2).
+// The LDS holds the dense matrix (NM x (NM + 1)).  With two waves each wave
+// takes every other row (left update) and column (right update) of a
+// reflector and every other column of Q, and the two partial dot products are
+// added through LDS: the serial chains of a step are half as long and twice as
+// many waves share a SIMD (the LDS allows four matrices per compute unit at
+// NM = 64).  Each lane holds its row of the wave's Q columns in registers.
+// Output: H = Q^T M Q (upper Hessenberg, exact zeros below the subdiagonal,
+// scaled by 2^-esc) in the T slot, Q in the Q slot, esc, and the status (0, or
+// the argument / non-finite code that ends the instance).
+template <int NW>
+TLA_DI void group_sync() {
+  if constexpr (NW > 1) __syncthreads();
+  else compiler_fence();
+}
+
+template <int NM, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 2 ? 2 : (NM == 64 ? 1 : (NM == 32 ? 4 : 5))))) void
 k_hess(SchurArgs g) {
   constexpr int LD = NM + 1;  // odd: row and column walks spread over the banks
+  constexpr int QN = NM / NW; // Schur-vector columns per wave: j = NW m + w
   __shared__ double Hs[NM * LD];
   __shared__ double vs_s[64];
+  __shared__ double px_s[2 * 64 * NW];  // the waves' partial dot products (matrix, Q)
+  __shared__ double red_s[2 * NW];
   lds_t<double>* H = to_lds(Hs);
   lds_t<double>* vs = to_lds(vs_s);
+  lds_t<double>* px = to_lds(px_s);
+  lds_t<double>* pq = px + 64 * NW;
   const int si = blockIdx.x / g.batch, b = blockIdx.x - si * g.batch;
   const SchurSet S = g.set[si];
-  const int l = lane_id();
+  const int l = lane_id(), w = NW > 1 ? (int)(threadIdx.x >> 6) : 0;
+  const bool t0 = threadIdx.x == 0;
   const int n = g.n[b];
   if (n < 0 || n > g.n_max) {
-    if (l == 0) S.status[b] = -1;
+    if (t0) S.status[b] = -1;
     return;
   }
   const int ldm = S.ldm[b];
   if (ldm < (n > 1 ? n : 1)) {
-    if (l == 0) S.status[b] = -2;
+    if (t0) S.status[b] = -2;
     return;
   }
   if (n == 0) {
-    if (l == 0) S.status[b] = 0;
+    if (t0) S.status[b] = 0;
     return;
   }
-  // ---- ingest: column j of M is read by the lanes (coalesced); M^T is stored transposed
+  // ---- ingest: column j of M is read by the lanes (coalesced), the waves
+  // taking every other column; M^T is stored transposed
   const gbl_t<double>* M = to_gbl(S.m[b]);
   bool finite = true;
   double amax = 0.0;
-  for (int j = 0; j < n; ++j) {
+  for (int j = w; j < n; j += NW) {
     if (l < n) {
       const double v = M[l + (size_t)j * ldm];
       finite = finite && __builtin_isfinite(v);
@@ -242,95 +260,134 @@ k_hess(SchurArgs g) {
       else H[l + j * LD] = v;
     }
   }
-  if (__any(!finite)) {
-    if (l == 0) S.status[b] = kGeNoConv;
+  amax = wave_max(amax);
+  const bool bad = __any(!finite);
+  if constexpr (NW > 1) {
+    if (l == 0) {
+      red_s[w] = amax;
+      red_s[NW + w] = bad ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    amax = fmax(red_s[0], red_s[1]);
+    if (red_s[NW] + red_s[NW + 1] != 0.0) {
+      if (t0) S.status[b] = kGeNoConv;
+      return;
+    }
+  } else if (bad) {
+    if (t0) S.status[b] = kGeNoConv;
     return;
   }
   // scale by a power of two (exact) so that the largest entry lies in [1/2, 1);
   // T is scaled back at the end, the Schur vectors do not depend on it
   int esc = 0;
-  amax = wave_max(amax);
   if (amax > 0.0) frexp(amax, &esc);
-  compiler_fence();
+  group_sync<NW>();
   if (esc != 0 && l < n)
-    for (int j = 0; j < n; ++j) H[l + j * LD] = ldexp(H[l + j * LD], -esc);
-  compiler_fence();
+    for (int j = w; j < n; j += NW) H[l + j * LD] = ldexp(H[l + j * LD], -esc);
+  group_sync<NW>();
 
-  double q[NM];
+  double q[QN];
 #pragma unroll
-  for (int j = 0; j < NM; ++j) q[j] = l == j ? 1.0 : 0.0;
+  for (int m = 0; m < QN; ++m) q[m] = l == NW * m + w ? 1.0 : 0.0;
 
   // ---- Householder reduction to upper Hessenberg form: H <- P H P, Q <- Q P,
   // P = I - tau v v^T zeroing column k below the subdiagonal (v_{k+1} = 1)
   for (int k = 0; k + 2 < n; ++k) {
     const double xi = (l > k && l < n) ? H[l + k * LD] : 0.0;
     const double ss = wave_sum(l > k + 1 ? xi * xi : 0.0);
-    if (ss == 0.0) continue;
+    if (ss == 0.0) continue;  // the same in both waves
     const double alpha = read_lane(xi, k + 1);
     const double beta = -copysign(sqrt(alpha * alpha + ss), alpha);
     const double tau = (beta - alpha) / beta;
     const double sc = 1.0 / (alpha - beta);
-    vs[l] = l == k + 1 ? 1.0 : (l > k + 1 ? xi * sc : 0.0);
-    compiler_fence();
-    // left: rows k+1..n-1 of columns k+1..n-1 (lane = column); the dot
-    // products below run as four interleaved partial sums
-    if (l > k && l < n) {
+    if (w == 0) vs[l] = l == k + 1 ? 1.0 : (l > k + 1 ? xi * sc : 0.0);
+    group_sync<NW>();
+    // left: rows k+1..n-1 of columns k+1..n-1 (lane = column, the wave's rows);
+    // the dot products run as four interleaved partial sums
+    auto left_dot = [&]() {
       double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
-      int i = k + 1;
+      int i = k + 1 + w;
 #pragma unroll 2
-      for (; i + 3 < n; i += 4) {
+      for (; i + 3 * NW < n; i += 4 * NW) {
         w0 += vs[i] * H[i + l * LD];
-        w1 += vs[i + 1] * H[i + 1 + l * LD];
-        w2 += vs[i + 2] * H[i + 2 + l * LD];
-        w3 += vs[i + 3] * H[i + 3 + l * LD];
+        w1 += vs[i + NW] * H[i + NW + l * LD];
+        w2 += vs[i + 2 * NW] * H[i + 2 * NW + l * LD];
+        w3 += vs[i + 3 * NW] * H[i + 3 * NW + l * LD];
       }
-      for (; i < n; ++i) w0 += vs[i] * H[i + l * LD];
-      const double w = tau * ((w0 + w1) + (w2 + w3));
+      for (; i < n; i += NW) w0 += vs[i] * H[i + l * LD];
+      return (w0 + w1) + (w2 + w3);
+    };
+    auto left_update = [&](double wl) {
 #pragma unroll 8
-      for (i = k + 1; i < n; ++i) H[i + l * LD] -= vs[i] * w;
-      H[l + k * LD] = l == k + 1 ? beta : 0.0;
-    }
-    compiler_fence();
-    // right: columns k+1..n-1 of every row (lane = row)
-    if (l < n) {
+      for (int i = k + 1 + w; i < n; i += NW) H[i + l * LD] -= vs[i] * wl;
+      if (w == 0) H[l + k * LD] = l == k + 1 ? beta : 0.0;
+    };
+    // right: columns k+1..n-1 of every row (lane = row, the wave's columns),
+    // and the Schur vectors' dot products (the wave's columns of Q)
+    auto right_dot = [&]() {
       double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
-      int j = k + 1;
+      int j = k + 1 + w;
 #pragma unroll 2
-      for (; j + 3 < n; j += 4) {
+      for (; j + 3 * NW < n; j += 4 * NW) {
         u0 += H[l + j * LD] * vs[j];
-        u1 += H[l + (j + 1) * LD] * vs[j + 1];
-        u2 += H[l + (j + 2) * LD] * vs[j + 2];
-        u3 += H[l + (j + 3) * LD] * vs[j + 3];
+        u1 += H[l + (j + NW) * LD] * vs[j + NW];
+        u2 += H[l + (j + 2 * NW) * LD] * vs[j + 2 * NW];
+        u3 += H[l + (j + 3 * NW) * LD] * vs[j + 3 * NW];
       }
-      for (; j < n; ++j) u0 += H[l + j * LD] * vs[j];
-      const double u = tau * ((u0 + u1) + (u2 + u3));
+      for (; j < n; j += NW) u0 += H[l + j * LD] * vs[j];
+      return (u0 + u1) + (u2 + u3);
+    };
+    auto right_update = [&](double u) {
 #pragma unroll 8
-      for (j = k + 1; j < n; ++j) H[l + j * LD] -= u * vs[j];
-    }
-    double uq[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int j = k + 1 + w; j < n; j += NW) H[l + j * LD] -= u * vs[j];
+    };
+    auto qdot = [&]() {
+      double uq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < NM; ++j) {
-      uq[j & 3] += q[j] * vs[j];
-      if ((j & 15) == 15) compiler_fence();  // a bounded number of v loads in flight
+      for (int m = 0; m < QN; ++m) {
+        uq[m & 3] += q[m] * vs[NW * m + w];
+        if ((m & 15) == 15) compiler_fence();  // a bounded number of v loads in flight
+      }
+      return (uq[0] + uq[1]) + (uq[2] + uq[3]);
+    };
+    double uqt;
+    if constexpr (NW == 1) {
+      if (l > k && l < n) left_update(tau * left_dot());
+      compiler_fence();
+      if (l < n) right_update(tau * right_dot());
+      uqt = qdot();
+    } else {
+      // the waves' partial sums are added through LDS (in a fixed order)
+      px[64 * w + l] = (l > k && l < n) ? left_dot() : 0.0;
+      __syncthreads();
+      if (l > k && l < n) left_update(tau * (px[l] + px[64 + l]));
+      __syncthreads();
+      px[64 * w + l] = l < n ? right_dot() : 0.0;
+      pq[64 * w + l] = qdot();
+      __syncthreads();
+      if (l < n) right_update(tau * (px[l] + px[64 + l]));
+      uqt = pq[l] + pq[64 + l];
     }
-    const double u = tau * ((uq[0] + uq[1]) + (uq[2] + uq[3]));
+    uqt *= tau;
 #pragma unroll
-    for (int j = 0; j < NM; ++j) {
-      q[j] -= u * vs[j];
-      if ((j & 15) == 15) compiler_fence();
+    for (int m = 0; m < QN; ++m) {
+      q[m] -= uqt * vs[NW * m + w];
+      if ((m & 15) == 15) compiler_fence();
     }
-    compiler_fence();
+    group_sync<NW>();
   }
   // ---- hand-off to the QR kernel through the output slots
   gbl_t<double>* T = to_gbl(S.t + (size_t)b * g.stride);
   gbl_t<double>* Q = to_gbl(S.q + (size_t)b * g.stride);
   const int ld = g.n_max;
-  for (int j = 0; j < n; ++j)
+  for (int j = w; j < n; j += NW)
     if (l < n) T[l + (size_t)j * ld] = H[l + j * LD];
 #pragma unroll
-  for (int j = 0; j < NM; ++j)
-    if (j < n && l < n) Q[l + (size_t)j * ld] = q[j];
-  if (l == 0) {
+  for (int m = 0; m < QN; ++m) {
+    const int j = NW * m + w;
+    if (j < n && l < n) Q[l + (size_t)j * ld] = q[m];
+  }
+  if (t0) {
     S.esc[b] = esc;
     S.status[b] = 0;
   }
@@ -768,13 +825,13 @@ tla_status ge_solve(tla_ctx* h, int op, tla_prec prec, int batch, int n_max, con
   if (syl) sa.set[1] = SchurSet{B, ldb, 0, 0, Ut, Wq, st1, esc1};
   const dim3 sg(batch * sa.nsets);
   if (nm <= 16) {
-    hipLaunchKernelGGL(k_hess<16>, sg, dim3(64), 0, h->stream, sa);
+    hipLaunchKernelGGL((k_hess<16, 1>), sg, dim3(64), 0, h->stream, sa);
     hipLaunchKernelGGL(k_schur_qr<16>, sg, dim3(64), 0, h->stream, sa);
   } else if (nm <= 32) {
-    hipLaunchKernelGGL(k_hess<32>, sg, dim3(64), 0, h->stream, sa);
+    hipLaunchKernelGGL((k_hess<32, 1>), sg, dim3(64), 0, h->stream, sa);
     hipLaunchKernelGGL(k_schur_qr<32>, sg, dim3(64), 0, h->stream, sa);
   } else {
-    hipLaunchKernelGGL(k_hess<64>, sg, dim3(64), 0, h->stream, sa);
+    hipLaunchKernelGGL((k_hess<64, 2>), sg, dim3(128), 0, h->stream, sa);
     hipLaunchKernelGGL(k_schur_qr<64>, sg, dim3(64), 0, h->stream, sa);
   }
   GE_HIP(hipGetLastError());
