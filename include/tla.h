@@ -186,6 +186,10 @@ tla_status tla_strlyap_batched(tla_handle h, int batch, int n_max, const int *n,
  *   (pointer arrays included) are device memory owned by the caller.  The
  *   handle keeps the Schur factors in a workspace of its own (4 n_max^2
  *   doubles per instance for gesyl, 2 for gelyap).
+ *   Each coefficient is scaled by a power of two before its reduction (its
+ *   largest entry into [1/2, 1), exact), so entries of any finite magnitude
+ *   are handled, and scaling A, B and C (A and S) by a common power of two
+ *   leaves X unchanged bit for bit.
  * The coefficients must have real eigenvalues (the triangular cores are
  * real): info[b] = -4 reports a complex conjugate pair, -5 a QR iteration
  * that did not converge or a non-finite coefficient entry; the instance's
