@@ -168,6 +168,33 @@ def test_gelyap_uneven_n(h, orc):
         assert rel_err(Xb[None], Xr[None]).max() <= TOL
 
 
+@pytest.mark.parametrize("prec", ["f64", "mixed_f32"])
+@pytest.mark.parametrize("n", [1, 7, 16, 33, 64])
+def test_triangular_coefficients_reduce_exactly(h, n, prec):
+    # A lower and B upper triangular are already in real Schur form: the
+    # reduction must find T_A = A^T and T_B = B with Z = W = I (no reflector,
+    # no rotation), the identity transforms are exact, so the general solves
+    # must equal the triangular ones bit for bit (a transposed factor, a
+    # swapped coefficient slot or an inexact scaling would show here)
+    batch = 4
+    L, U, C = I.trsyl_problem(f"ge-tri-{n}", n, batch)
+    print(f"gesyl triangular n={n} {prec}", flush=True)
+    X, info = run_gesyl(h, L, U, C, prec)
+    dL, dU, dC = tla.to_device_cm(L), tla.to_device_cm(U), tla.to_device_cm(C)
+    ops = tla.trsyl(h, dL, dU, dC, prec)
+    torch.cuda.synchronize()
+    assert np.all(info == 0) and np.all(ops.info.cpu().numpy() == 0)
+    assert np.array_equal(X, tla.from_device_cm(dC))
+    L, S = I.trlyap_problem(f"ge-tri-{n}", n, batch)
+    print(f"gelyap triangular n={n} {prec}", flush=True)
+    X, info = run_gelyap(h, L, S, prec)
+    dL, dS = tla.to_device_cm(L), tla.to_device_cm(np.tril(S))
+    ops = tla.trlyap(h, dL, dS, prec)
+    torch.cuda.synchronize()
+    assert np.all(info == 0) and np.all(ops.info.cpu().numpy() == 0)
+    assert np.array_equal(X, tla.from_device_cm(dS))
+
+
 @pytest.mark.parametrize("p", [600, -600])
 def test_power_of_two_scale_invariance(h, p):
     # A, B, C (and A, S) scaled by 2^p leave X unchanged.  The front end scales
