@@ -110,7 +110,7 @@ TLA_DI double rot_lo(double c, double s, double a, double b) { return __builtin_
 // first moved by 2^-500 away from zero, which leaves every |x| >= 2^-446
 // unchanged (less than half its last place) and keeps x^2 + y^2 >= 2^-1000:
 // a pair below that (far under the working precision of such a matrix) gets a
-// rotation onto (x', y), the identity for x = y = 0.
+// rotation onto (x', y): c = +-1, s = 0 for x = +-0, y = 0.
 TLA_DI void givens_chase(double x, double y, double& c, double& s) {
   const double xe = x + copysign(0x1p-500, x);
   const double r2 = __builtin_fma(xe, xe, y * y);
